@@ -1,0 +1,202 @@
+"""CPU FP64 oracle for the Barnes-Hut tree method (arXiv:1112.4539).
+
+TEST INFRASTRUCTURE.  Only the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the GPU library never
+does, and this package imports nothing from it.
+
+The arithmetic lives in ``bh_oracle.c`` (plain C, binary64, no FP contraction);
+this module only loads it and marshals numpy arrays.  Definitions followed:
+
+* ``direct``      -- Sec. 3, Eq. (1): softened pair sum over j != i.  The
+  acceleration is attractive, the potential is the physical ``-sum m/r``.
+* ``Tree``        -- Sec. 4.1 recursive oct-tree on the 2^21 grid of the root
+  cube, compressed, with the Sec. 4.4 monopole moments and Eq. (2) cell sizes.
+* ``Tree.walk``   -- Fig. 3 recursive walk with the opening test of Eq. (2)/(3).
+* ``rms_rel_err`` / ``mean_rel_err`` -- Sec. 5, Eq. (4) and its RMS form.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bh_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``bh_oracle.c`` into ``liboracle.so`` with gcc (OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+             "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    d = ctypes.c_double
+    lib.orc_direct.argtypes = [P, P, i64, P, i64, d, P, P, P]
+    lib.orc_direct.restype = ctypes.c_int
+    lib.orc_tree_build.argtypes = [P, P, i64]
+    lib.orc_tree_build.restype = P
+    lib.orc_tree_free.argtypes = [P]
+    lib.orc_tree_free.restype = None
+    lib.orc_tree_nodes.argtypes = [P]
+    lib.orc_tree_nodes.restype = i64
+    lib.orc_tree_cube.argtypes = [P, P, P]
+    lib.orc_tree_cube.restype = None
+    lib.orc_tree_export.argtypes = [P] * 12
+    lib.orc_tree_export.restype = None
+    lib.orc_walk.argtypes = [P, P, i64, d, P, d, P, P, P, P, P, P, P, i64]
+    lib.orc_walk.restype = ctypes.c_int
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _as_pos(pos):
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    if pos.ndim != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be [n, 3]")
+    return pos
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def direct(pos, mass, eps, targets=None):
+    """Direct sum of Eq. (1) for ``targets`` (all particles if None).
+
+    Returns ``(acc [nt,3], pot [nt], amag [nt])`` in float64, where ``amag`` is
+    the sum of the magnitudes of the acceleration terms.
+    """
+    lib = _load()
+    pos = _as_pos(pos)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = pos.shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    acc = np.zeros((nt, 3))
+    pot = np.zeros(nt)
+    amag = np.zeros(nt)
+    rc = lib.orc_direct(_ptr(pos), _ptr(mass), n, _ptr(tg), nt, float(eps),
+                        _ptr(acc), _ptr(pot), _ptr(amag))
+    if rc != 0:
+        raise ValueError("orc_direct rejected its arguments")
+    return acc, pot, amag
+
+
+class Tree:
+    """Oracle oct-tree of ``n`` particles (Sec. 4.1), nodes in depth-first preorder."""
+
+    def __init__(self, pos, mass):
+        lib = _load()
+        self.pos = _as_pos(pos)
+        self.mass = np.ascontiguousarray(mass, dtype=np.float64)
+        if self.mass.shape != (self.pos.shape[0],):
+            raise ValueError("mass must be [n]")
+        self.n = self.pos.shape[0]
+        self._h = lib.orc_tree_build(_ptr(self.pos), _ptr(self.mass), self.n)
+        if not self._h:
+            raise MemoryError("oracle tree build failed")
+        self.n_nodes = int(lib.orc_tree_nodes(self._h))
+        lo = np.zeros(3)
+        L = np.zeros(1)
+        lib.orc_tree_cube(self._h, _ptr(lo), _ptr(L))
+        self.lo, self.L = lo, float(L[0])
+        m = self.n_nodes
+        self.level = np.zeros(m, np.int32)
+        self.first = np.zeros(m, np.int32)
+        self.count = np.zeros(m, np.int32)
+        self.next = np.zeros(m, np.int32)
+        self.leaf = np.zeros(m, np.int8)
+        self.cell = np.zeros((m, 3), np.int64)
+        self.com = np.zeros((m, 3))
+        self.M = np.zeros(m)
+        self.s = np.zeros(m)
+        self.l = np.zeros(m)
+        self.perm = np.zeros(self.n, np.int64)
+        lib.orc_tree_export(self._h, _ptr(self.level), _ptr(self.first), _ptr(self.count),
+                            _ptr(self.next), _ptr(self.leaf), _ptr(self.cell), _ptr(self.com),
+                            _ptr(self.M), _ptr(self.s), _ptr(self.l), _ptr(self.perm))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().orc_tree_free(h)
+            self._h = None
+
+    def walk(self, theta, eps, targets=None, theta_per_target=None, maxlen=0):
+        """Fig. 3 walk for ``targets`` (original indices; all if None).
+
+        Returns a dict with ``acc [nt,3]``, ``pot``, ``amag``, ``n_pp``, ``n_pc``,
+        ``hash`` (uint64 ordered-list hash) and, if ``maxlen`` > 0, ``lists``
+        ([nt, maxlen] int64 words, -1 padded; word = j<<1 for a particle term with
+        original index j, node<<1|1 for a cell term with preorder id node).
+        """
+        lib = _load()
+        tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+        nt = self.n if tg is None else tg.shape[0]
+        tpt = None
+        if theta_per_target is not None:
+            tpt = np.ascontiguousarray(theta_per_target, dtype=np.float64)
+            if tpt.shape != (nt,):
+                raise ValueError("theta_per_target must have one value per target")
+        out = dict(acc=np.zeros((nt, 3)), pot=np.zeros(nt), amag=np.zeros(nt),
+                   n_pp=np.zeros(nt, np.int64), n_pc=np.zeros(nt, np.int64),
+                   hash=np.zeros(nt, np.uint64))
+        lists = None
+        if maxlen > 0:
+            lists = np.full((nt, maxlen), -1, np.int64)
+        rc = lib.orc_walk(self._h, _ptr(tg), nt, float(theta), _ptr(tpt), float(eps),
+                          _ptr(out["acc"]), _ptr(out["pot"]), _ptr(out["amag"]),
+                          _ptr(out["n_pp"]), _ptr(out["n_pc"]), _ptr(out["hash"]),
+                          _ptr(lists), int(maxlen))
+        if rc != 0:
+            raise ValueError("orc_walk rejected its arguments")
+        if lists is not None:
+            out["lists"] = lists
+        return out
+
+
+def rms_rel_err(a, a_ref):
+    """RMS over particles of |a - a_ref| / |a_ref| (the RMS form of Eq. (4))."""
+    a = np.asarray(a, np.float64)
+    a_ref = np.asarray(a_ref, np.float64)
+    if a.ndim == 1:
+        r = np.abs(a - a_ref) / np.abs(a_ref)
+    else:
+        r = np.linalg.norm(a - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
+    return float(np.sqrt(np.mean(r * r)))
+
+
+def mean_rel_err(a, a_ref):
+    """Mean over particles of |a - a_ref| / |a_ref|, Eq. (4)."""
+    a = np.asarray(a, np.float64)
+    a_ref = np.asarray(a_ref, np.float64)
+    if a.ndim == 1:
+        r = np.abs(a - a_ref) / np.abs(a_ref)
+    else:
+        r = np.linalg.norm(a - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
+    return float(np.mean(r))
