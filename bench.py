@@ -1,0 +1,199 @@
+"""Benchmark of the tree-force hot path on one MI355X.
+
+One step = build the tree (bbox, Morton keys, radix sort, topology, FP64
+moments) + the force walk for every particle, on the 4,194,304-particle clumpy
+field (25% uniform in the unit cube + 64 Plummer clumps, a = 0.01), FP32
+inputs, eps = 1e-4, at the opening parameter that reaches an RMS relative
+force error <= 1e-3 against the direct sum (checked on 65,536 sampled targets
+with the GPU FP64 direct sum, outside the timed region).
+
+Prints one JSON line.  ``value`` = particle interactions per second of the
+whole step (interactions counted by the instrumented walk, identical lists).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+METRIC = "particle-interactions/s and forces/s at RMS rel force err 1e-3, N=4M, 1 GPU"
+FLOPS_PER_INTERACTION = 38          # the paper's conventional count (Sec. 3)
+PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pos32, mass32, theta, eps, seed, n_sample):
+    """The FP64 CPU oracle on this host: full tree build + walk of a target sample, scaled."""
+    import oracle
+    p64 = pos32.astype(np.float64)
+    m64 = mass32.astype(np.float64)
+    t0 = time.perf_counter()
+    T = oracle.Tree(p64, m64)
+    t1 = time.perf_counter()
+    from paper_1112_4539_amd import inputs
+    tg = inputs.sample_targets(len(p64), n_sample, seed + 7)
+    w = T.walk(theta, eps, targets=tg)
+    t2 = time.perf_counter()
+    n = len(p64)
+    inter = float(np.sum(w["n_pp"] + w["n_pc"]))
+    scale = n / len(tg)
+    t_total = (t1 - t0) + (t2 - t1) * scale
+    return dict(value=inter * scale / t_total, unit="interactions/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"FP64 oracle: tree build of all {n} particles ({t1 - t0:.2f} s) + walk of {len(tg)} "
+                       f"sampled targets ({t2 - t1:.2f} s), walk time scaled by {scale:.1f} to all targets",
+                build_s=t1 - t0, walk_sample_s=t2 - t1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clumpy4m")
+    ap.add_argument("--theta", type=float, default=0.35)
+    ap.add_argument("--samples", type=int, default=65536, help="targets of the accuracy check")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=262144)
+    ap.add_argument("--waves-per-block", type=int, default=4)
+    ap.add_argument("--xcd-chunk", type=int, default=0)
+    ap.add_argument("--target-order", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1112_4539_amd as bh
+    from paper_1112_4539_amd import inputs
+
+    pos, mass, spec = inputs.make(args.workload)
+    eps = spec["eps"]
+    n = len(pos)
+    pos32 = pos.astype(np.float32)
+    mass32 = mass.astype(np.float32)
+    dev = torch.device("cuda:0")
+    gpos = torch.tensor(pos32, device=dev)
+    gmass = torch.tensor(mass32, device=dev)
+    ws = torch.empty(bh.workspace_bytes(n, bh.FP32), dtype=torch.uint8, device=dev)
+    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((n,), dtype=torch.float32, device=dev)
+    log(f"[bench] workload={args.workload} n={n} theta={args.theta} eps={eps}")
+
+    def step():
+        T = bh.Tree(gpos, gmass, workspace=ws)
+        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order)
+        T.forces(args.theta, eps, acc=acc, pot=pot)
+        return T
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # interaction count of one step (the instrumented walk meets the same lists)
+    T = bh.Tree(gpos, gmass, workspace=ws)
+    T.check()
+    st = T.walk_stats(args.theta, eps)
+    counts = st["counts"].to(torch.int64)
+    inter = int(counts.sum().item())
+    n_pp = int(counts[:, 0].sum().item())
+    tstats = T.stats()
+    del st, T
+    torch.cuda.synchronize()
+    log(f"[bench] interactions/step={inter} nodes={tstats['n_nodes']}")
+
+    # timed steps
+    walk_ms = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        T = bh.Tree(gpos, gmass, workspace=ws)
+        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order)
+        T.set_timing(True)
+        T.forces(args.theta, eps, acc=acc, pot=pot)
+        walk_ms.append(T)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    walk = [T.walk_time_ms() for T in walk_ms]
+    del walk_ms
+    walk_avg = float(np.mean(walk))
+    log(f"[bench] ms/step={ms_step:.3f} (wall {wall_ms:.3f})  walk kernel {walk_avg:.3f} ms")
+
+    # build alone
+    ev0.record()
+    for _ in range(args.steps):
+        bh.Tree(gpos, gmass, workspace=ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    build_ms = ev0.elapsed_time(ev1) / args.steps
+
+    rms = None
+    if not args.no_accuracy:
+        tg = torch.tensor(inputs.sample_targets(n, args.samples, spec["seed"]), device=dev)
+        a_ref, _ = bh.direct(gpos.double(), gmass.double(), eps, tg)
+        T = bh.Tree(gpos, gmass, workspace=ws)
+        a, _ = T.forces(args.theta, eps, acc=acc, pot=pot)
+        d = (a[tg].double() - a_ref).norm(dim=1) / a_ref.norm(dim=1)
+        rms = float(torch.sqrt(torch.mean(d * d)).item())
+        log(f"[bench] RMS rel force err vs FP64 direct on {args.samples} targets: {rms:.3e}")
+
+    value = inter / (ms_step * 1e-3)
+    achieved = FLOPS_PER_INTERACTION * inter / (walk_avg * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"clumpy field N={n} (25% uniform in the unit cube + 64 Plummer clumps a=0.01, R=0.1), "
+                        f"seed {spec['seed']}, eps={eps}, theta={args.theta}, FP32 in/out",
+            "n": n, "theta": args.theta, "eps": eps,
+            "interactions_per_step": inter, "particle_terms_per_step": n_pp,
+            "forces_per_s": n / (ms_step * 1e-3),
+            "build_ms": build_ms, "walk_ms": walk_avg,
+            "walk_interactions_per_s": inter / (walk_avg * 1e-3),
+            "rms_rel_force_err": rms, "accuracy_targets": None if rms is None else args.samples,
+            "n_nodes": tstats["n_nodes"],
+            "launch": {"waves_per_block": args.waves_per_block, "xcd_chunk": args.xcd_chunk,
+                       "target_order": args.target_order},
+        },
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "kernel": "bh::k_walk<false,0>", "flops_per_unit": FLOPS_PER_INTERACTION,
+            "units_per_launch": inter,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        cb = cpu_baseline(pos32, mass32, args.theta, eps, spec["seed"], args.cpu_sample)
+        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * bh.h -- C ABI of the gfx950 Barnes-Hut tree library.
+ *
+ * Method: N. Nakasato, "Implementation of a Parallel Tree Method on a GPU"
+ * (arXiv:1112.4539).  The library builds the oct-tree of Sec. 4.1 on the GPU
+ * (particles in the localized Morton order of Sec. 5), and evaluates the
+ * softened gravity of Eq. (1) with the iterative next/more tree walk of
+ * Sec. 4.4 and the opening criterion of Eq. (2)/(3).
+ *
+ * Conventions for every entry point:
+ *   - Particle arrays are DEVICE pointers in the caller's order: positions
+ *     [n][3] row-major (x, y, z), masses [n], both float (BH_FP32) or double
+ *     (BH_FP64), aligned to their element size.  Outputs are device arrays in
+ *     the same caller order: acc [n][3], pot [n], same precision as the input.
+ *   - The caller owns every buffer, including the workspace (>= 256-byte
+ *     aligned); the library allocates no device memory.  A tree handle is a
+ *     small host object holding views into the workspace: it must not outlive
+ *     the workspace or the input arrays' contents it was built from, and is
+ *     freed with bh_tree_release().
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it; calls return before the GPU finishes.  Errors found on
+ *     the host are returned at once; errors of the GPU work surface on a later
+ *     call that synchronises (bh_tree_check, bh_tree_stats, bh_walk_time_ms).
+ *   - Return value: BH_OK (0) or a negative status; bh_last_error() gives the
+ *     text of the last failure of the calling thread.
+ *   - Units: G = 1.  The acceleration on i points toward the sources
+ *     (attractive) and the potential is the physical, negative -sum m_j/r.
+ *   - Bit-identical results for identical inputs and parameters, whatever the
+ *     launch shape (bh_set_walk_config) or target order.
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define BH_API __attribute__((visibility("default")))
+#else
+#define BH_API
+#endif
+
+typedef struct bh_tree bh_tree;
+
+#define BH_FP32 0
+#define BH_FP64 1
+
+#define BH_OK 0
+#define BH_EINVAL (-1) /* bad argument: n, pointer, alignment, theta, eps, non-finite input */
+#define BH_ENOSPC (-2) /* workspace smaller than bh_workspace_bytes() */
+#define BH_EHIP (-3)   /* HIP runtime error; see bh_last_error() */
+
+/* Text of the last error of the calling thread ("" if none). */
+BH_API const char *bh_last_error(void);
+
+/* ABI version of this library (bumped on any incompatible change). */
+BH_API int bh_version(void);
+
+/* Bytes of workspace a tree of n particles in precision prec needs (an upper
+ * bound: the compressed oct-tree has at most 2n-1 nodes).  Returns -1 for an
+ * invalid n (n < 0 or n > 2^30) or prec. */
+BH_API int64_t bh_workspace_bytes(int64_t n, int prec);
+
+/* Build the tree of n particles (Sec. 4.1 construction; Sec. 5 Morton order;
+ * Sec. 4.4 cell mass, centre of mass and next pointers; Eq. (2) distance s
+ * from the cell centre to the centre of mass).
+ *   pos [n][3], mass [n]: device, precision prec; must stay unchanged while
+ *                        the tree is used (the walk reads sorted copies, but
+ *                        bh_tree_check validates the inputs by their bbox pass).
+ *   workspace, ws_bytes: device buffer of at least bh_workspace_bytes(n, prec).
+ *   out: receives the new handle (host object).
+ * The root cube is the coordinate-wise minimum corner with side = the largest
+ * extent; cells are cut on its 2^21 grid; a finest-grid cell holding several
+ * particles is one leaf.  Non-finite coordinates or masses are flagged on the
+ * device and reported by bh_tree_check().  n = 0 is allowed (empty tree). */
+BH_API int bh_build_tree(const void *pos, const void *mass, int64_t n, int prec, void *workspace,
+                  int64_t ws_bytes, void *stream, bh_tree **out);
+
+/* Synchronise `stream` and report whether the inputs of the build were finite
+ * (BH_EINVAL if not) and whether the GPU work failed (BH_EHIP). */
+BH_API int bh_tree_check(const bh_tree *t, void *stream);
+
+/* Synchronise `stream` and read the node counts of the tree (any pointer may be NULL). */
+BH_API int bh_tree_stats(const bh_tree *t, void *stream, int64_t *n_nodes, int64_t *n_leaves, int64_t *n_internal);
+
+/* Forces on every particle by the tree walk (Sec. 4.4, Fig. 5; opening test
+ * Eq. (2): a cell not holding i is used whole iff d^2 > (l/theta + s)^2, d the
+ * distance from x_i to the cell's centre of mass, l its side).  Particle and
+ * cell terms both use the softened kernel of Eq. (1) with softening eps.
+ *   theta: in (0, 2/sqrt(3)) -- beyond it a cell could be accepted by a
+ *          particle inside it.  eps >= 0 and finite.
+ *   acc [n][3], pot [n]: device outputs, caller order, tree precision.
+ * BH_FP32 trees evaluate terms in FP32 with FP64 opening tests and cell
+ * offsets and compensated FP32 sums; BH_FP64 trees evaluate in FP64. */
+BH_API int bh_forces(const bh_tree *t, double theta, double eps, void *acc, void *pot, void *stream);
+
+/* Same walk with one opening parameter per Morton group of 64 particles:
+ * theta_group [ceil(n/64)] device floats, each in (0, 2/sqrt(3)) (not checked
+ * on the device); group g holds the particles at Morton positions [64g, 64g+64). */
+BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double eps, void *acc, void *pot,
+                    void *stream);
+
+/* The walk of bh_forces / bh_forces_theta (theta_group may be NULL) that also
+ * records, per particle in caller order, counts [n][2] = (particle terms, cell
+ * terms) and hash [n] = ordered-list hash: h = (h xor w) * 1099511628211 from
+ * h = 14695981039346656037 over the list words w, w = j<<1 for a particle term
+ * with source j (caller index), w = c<<1|1 for a cell term with node c
+ * (depth-first preorder id).  If lists != NULL it also writes the first maxlen
+ * words of each list to lists [n][maxlen] (entries past the list are left as
+ * they were). */
+BH_API int bh_walk_stats(const bh_tree *t, double theta, const float *theta_group, double eps, void *acc,
+                  void *pot, int32_t *counts, uint64_t *hash, int64_t *lists, int64_t maxlen,
+                  void *stream);
+
+/* Copy the tree out for inspection: nodes (device, n_nodes records of 64
+ * bytes: double com[3], M, l, s; int32 next, first, count, meta with bit 0 =
+ * leaf and bits 8-15 = level) and perm [n] (device int32: Morton position ->
+ * caller index).  Either pointer may be NULL.  Synchronises the stream. */
+BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *stream);
+
+/* Launch shape of the walk: waves_per_block in {1, 2, 4}; xcd_chunk >= 0
+ * (runs of workgroups kept on one XCD; 0 = plain order).  target_order 0 =
+ * Morton order (groups of Morton-consecutive targets), 1 = caller order (the
+ * paper's unsorted experiment, Sec. 5).  Results do not depend on any of them. */
+BH_API int bh_set_walk_config(bh_tree *t, int waves_per_block, int xcd_chunk, int target_order);
+
+/* Enable (1) or disable (0) HIP-event timing of the walk kernel; after a
+ * timed walk, bh_walk_time_ms synchronises and returns its duration. */
+BH_API int bh_set_timing(bh_tree *t, int enable);
+BH_API int bh_walk_time_ms(const bh_tree *t, float *ms);
+
+/* Release a tree handle (host object only; the workspace stays the caller's). */
+BH_API void bh_tree_release(bh_tree *t);
+
+/* Brute-force sum of Eq. (1) over all j != i for nt targets (Sec. 3):
+ * pos [n][3], mass [n] device in precision prec; targets [nt] device int64
+ * caller indices in [0, n); acc [nt][3], pot [nt] device outputs in target
+ * order.  eps >= 0.  BH_FP64 follows the reference expression in ascending j. */
+BH_API int bh_direct(const void *pos, const void *mass, int64_t n, int prec, const int64_t *targets,
+              int64_t nt, double eps, void *acc, void *pot, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BH_H */

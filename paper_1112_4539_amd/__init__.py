@@ -1,0 +1,246 @@
+"""gfx950 Barnes-Hut tree forces (arXiv:1112.4539), Python binding of ``libbh.so``.
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels (declared in ``include/bh.h``).  torch provides device memory and the
+stream; it must be imported before the library is loaded so that both use
+the same HIP runtime.  There is no fallback: if ``libbh.so`` is missing or a
+call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+__all__ = ["Tree", "build_tree", "direct", "workspace_bytes", "load", "THETA_MAX",
+           "BHError", "FP32", "FP64"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbh.so")
+FP32, FP64 = 0, 1
+THETA_MAX = 2.0 / math.sqrt(3.0)
+
+_lib = None
+
+
+class BHError(RuntimeError):
+    pass
+
+
+def load():
+    """Load ``libbh.so`` (built by ``paper_1112_4539_amd/build.py``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BHError(f"{LIB_PATH} is not built; run `python paper_1112_4539_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    sig = {
+        "bh_last_error": ([], ctypes.c_char_p),
+        "bh_version": ([], i32),
+        "bh_workspace_bytes": ([i64, i32], i64),
+        "bh_build_tree": ([P, P, i64, i32, P, i64, P, P], i32),
+        "bh_tree_check": ([P, P], i32),
+        "bh_tree_stats": ([P, P, P, P, P], i32),
+        "bh_forces": ([P, d, d, P, P, P], i32),
+        "bh_forces_theta": ([P, P, d, P, P, P], i32),
+        "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P], i32),
+        "bh_tree_export": ([P, P, P, P], i32),
+        "bh_set_walk_config": ([P, i32, i32, i32], i32),
+        "bh_set_timing": ([P, i32], i32),
+        "bh_walk_time_ms": ([P, P], i32),
+        "bh_tree_release": ([P], None),
+        "bh_direct": ([P, P, i64, i32, P, i64, d, P, P, P], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = load().bh_last_error().decode()
+        if rc == -1:
+            raise ValueError(msg)
+        raise BHError(f"status {rc}: {msg}")
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _prec_of(dtype):
+    if dtype == torch.float32:
+        return FP32
+    if dtype == torch.float64:
+        return FP64
+    raise TypeError("positions and masses must be float32 or float64")
+
+
+def workspace_bytes(n, prec):
+    v = load().bh_workspace_bytes(int(n), int(prec))
+    if v < 0:
+        raise ValueError(f"invalid n={n} or precision={prec}")
+    return int(v)
+
+
+NODE_DTYPE = None
+
+
+def _node_dtype():
+    import numpy as np
+    global NODE_DTYPE
+    if NODE_DTYPE is None:
+        NODE_DTYPE = np.dtype([("com", "<f8", (3,)), ("M", "<f8"), ("l", "<f8"), ("s", "<f8"),
+                               ("next", "<i4"), ("first", "<i4"), ("count", "<i4"), ("meta", "<i4")])
+    return NODE_DTYPE
+
+
+class Tree:
+    """Oct-tree of one particle set on the GPU (``bh_build_tree``).
+
+    ``pos`` [n,3] and ``mass`` [n] are CUDA tensors of one float dtype; the tree
+    keeps references to them and to its workspace tensor.
+    """
+
+    def __init__(self, pos, mass, workspace=None):
+        lib = load()
+        if pos.device.type != "cuda" or mass.device.type != "cuda":
+            raise ValueError("pos and mass must be device tensors")
+        if pos.dtype != mass.dtype:
+            raise TypeError("pos and mass must have the same dtype")
+        self.prec = _prec_of(pos.dtype)
+        self.pos = pos.contiguous()
+        self.mass = mass.contiguous()
+        if self.pos.dim() != 2 or self.pos.shape[1] != 3 or self.mass.shape != (self.pos.shape[0],):
+            raise ValueError("pos must be [n,3] and mass [n]")
+        self.n = int(self.pos.shape[0])
+        self.device = self.pos.device
+        need = workspace_bytes(self.n, self.prec)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.workspace = workspace
+        h = ctypes.c_void_p()
+        _check(lib.bh_build_tree(_ptr(self.pos), _ptr(self.mass), self.n, self.prec, _ptr(workspace),
+                                 workspace.numel(), _stream(self.device), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load().bh_tree_release(h)
+            self._h = None
+
+    @property
+    def dtype(self):
+        return self.pos.dtype
+
+    def check(self):
+        """Synchronise; raise ValueError if an input coordinate or mass was not finite."""
+        _check(load().bh_tree_check(self._h, _stream(self.device)))
+
+    def stats(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().bh_tree_stats(self._h, _stream(self.device), ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)))
+        return dict(n_nodes=a.value, n_leaves=b.value, n_internal=c.value)
+
+    def set_walk_config(self, waves_per_block=4, xcd_chunk=0, target_order=0):
+        _check(load().bh_set_walk_config(self._h, int(waves_per_block), int(xcd_chunk), int(target_order)))
+
+    def set_timing(self, enable=True):
+        _check(load().bh_set_timing(self._h, 1 if enable else 0))
+
+    def walk_time_ms(self):
+        ms = ctypes.c_float()
+        _check(load().bh_walk_time_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def _outs(self, acc, pot):
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=self.dtype, device=self.device)
+        if pot is None:
+            pot = torch.empty((self.n,), dtype=self.dtype, device=self.device)
+        if acc.dtype != self.dtype or pot.dtype != self.dtype or not acc.is_contiguous() \
+                or not pot.is_contiguous() or acc.shape != (self.n, 3) or pot.shape != (self.n,):
+            raise ValueError("acc must be [n,3] and pot [n], contiguous, in the tree's dtype")
+        return acc, pot
+
+    def _theta_group(self, theta_group):
+        if theta_group is None:
+            return None
+        g = (self.n + 63) // 64
+        if theta_group.shape != (g,) or theta_group.dtype != torch.float32 or theta_group.device != self.device:
+            raise ValueError(f"theta_group must be a float32 device tensor of shape [{g}]")
+        return theta_group.contiguous()
+
+    def forces(self, theta=0.5, eps=0.0, acc=None, pot=None, theta_group=None):
+        """Tree-walk accelerations [n,3] and potentials [n] (``bh_forces`` / ``bh_forces_theta``)."""
+        acc, pot = self._outs(acc, pot)
+        lib = load()
+        tg = self._theta_group(theta_group)
+        if tg is None:
+            _check(lib.bh_forces(self._h, float(theta), float(eps), _ptr(acc), _ptr(pot), _stream(self.device)))
+        else:
+            _check(lib.bh_forces_theta(self._h, _ptr(tg), float(eps), _ptr(acc), _ptr(pot),
+                                       _stream(self.device)))
+        return acc, pot
+
+    def walk_stats(self, theta=0.5, eps=0.0, theta_group=None, maxlen=0):
+        """Forces plus per-particle (particle terms, cell terms), list hash and optional list dump."""
+        acc, pot = self._outs(None, None)
+        counts = torch.empty((self.n, 2), dtype=torch.int32, device=self.device)
+        hsh = torch.empty((self.n,), dtype=torch.int64, device=self.device)
+        lists = None
+        if maxlen > 0:
+            lists = torch.full((self.n, maxlen), -1, dtype=torch.int64, device=self.device)
+        tg = self._theta_group(theta_group)
+        _check(load().bh_walk_stats(self._h, float(theta), _ptr(tg), float(eps), _ptr(acc), _ptr(pot),
+                                    _ptr(counts), _ptr(hsh), _ptr(lists), int(maxlen), _stream(self.device)))
+        out = dict(acc=acc, pot=pot, counts=counts, hash=hsh)
+        if lists is not None:
+            out["lists"] = lists
+        return out
+
+    def export(self):
+        """Node records (numpy structured array, preorder) and perm (Morton position -> caller index)."""
+        import numpy as np
+        st = self.stats()
+        m = st["n_nodes"]
+        nodes = torch.empty((max(m, 1) * 64,), dtype=torch.uint8, device=self.device)
+        perm = torch.empty((max(self.n, 1),), dtype=torch.int32, device=self.device)
+        _check(load().bh_tree_export(self._h, _ptr(nodes), _ptr(perm), _stream(self.device)))
+        rec = nodes.cpu().numpy()[: m * 64].view(_node_dtype())
+        return rec, perm.cpu().numpy()[: self.n].astype(np.int64)
+
+
+def build_tree(pos, mass, workspace=None):
+    return Tree(pos, mass, workspace)
+
+
+def direct(pos, mass, eps, targets=None):
+    """Brute-force Eq. (1) for ``targets`` (int64 device tensor of caller indices; all if None)."""
+    lib = load()
+    prec = _prec_of(pos.dtype)
+    pos = pos.contiguous()
+    mass = mass.contiguous()
+    n = int(pos.shape[0])
+    if targets is None:
+        targets = torch.arange(n, dtype=torch.int64, device=pos.device)
+    targets = targets.to(torch.int64).contiguous()
+    nt = int(targets.shape[0])
+    acc = torch.empty((nt, 3), dtype=pos.dtype, device=pos.device)
+    pot = torch.empty((nt,), dtype=pos.dtype, device=pos.device)
+    _check(lib.bh_direct(_ptr(pos), _ptr(mass), n, prec, _ptr(targets), nt, float(eps), _ptr(acc), _ptr(pot),
+                         _stream(pos.device)))
+    return acc, pot

@@ -1,0 +1,667 @@
+// bh_build.hip -- tree construction on the GPU (gfx950).
+//
+// The paper builds the oct-tree on the host (Sec. 4.1, and steps 1-3 of the
+// flow listed at the end of Sec. 4.4) and suggests parallelising that part
+// (Sec. 7).  Here every step runs on the device, as a pipeline of HBM-bound
+// passes with no host round trip:
+//
+//   bbox     root cube: coordinate-wise min, largest extent L       (Sec. 4.1)
+//   keys     63-bit Morton key on the 2^21 grid of the cube         (Sec. 5)
+//   sort     stable LSD radix sort of (key, index), 8 x 8-bit digits (Sec. 5,
+//            localized particle ordering), then gather to Morton order
+//   topology compressed oct-tree read off the sorted unique keys; nodes are
+//            numbered in depth-first preorder, so more(c) = c+1 and
+//            next(c) = c + subtree size (Sec. 4.4, next/more pointers)
+//   moments  FP64 mass and centre of mass, children folded left in octant
+//            order, one pass per tree level, deepest first (Sec. 4.4), and
+//            the distance s of Eq. (2)
+//
+// Determinism: integer work is exact; the FP64 sums have a fixed order and use
+// only correctly rounded +, *, /, sqrt and fma, so the node set and every node
+// value are bit-identical from run to run and independent of launch shapes.
+#include "bh_internal.h"
+
+namespace bh {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Exclusive block scan of one value per thread (blockDim.x = nwaves*64).
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int* lds, int* total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int x = wave_incl_scan(v, lane);
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) {
+    int s = lds[k];
+    pre += (k < w) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------- scan (int32)
+// Device-wide exclusive scan: tile sums, scan of tile sums, per-tile apply.
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in, int n,
+                                                               int32_t* __restrict__ tile_sums) {
+  __shared__ int lds[kScanThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int s = 0;
+#pragma unroll 4
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r * kScanThreads + threadIdx.x;
+    s += (i < n) ? in[i] : 0;
+  }
+  int tot;
+  block_excl_scan<kScanThreads>(s, lds, &tot);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of the tile sums in place; total to *total.
+__global__ __launch_bounds__(1024) void k_scan_tiles(int32_t* __restrict__ sums, int ntiles,
+                                                     int32_t* __restrict__ total) {
+  __shared__ int lds[16];
+  const int t = threadIdx.x;
+  int per = (ntiles + 1023) / 1024;
+  int b = t * per, e = min(ntiles, b + per);
+  int s = 0;
+  for (int k = b; k < e; ++k) s += sums[k];
+  int tot;
+  int pre = block_excl_scan<1024>(s, lds, &tot);
+  for (int k = b; k < e; ++k) {
+    int v = sums[k];
+    sums[k] = pre;
+    pre += v;
+  }
+  if (t == 0 && total) *total = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* __restrict__ in, int n,
+                                                              const int32_t* __restrict__ tile_offs,
+                                                              int32_t* __restrict__ out) {
+  __shared__ int tile[kScanTile];
+  __shared__ int lds[kScanThreads / 64];
+  const int t = threadIdx.x;
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r * kScanThreads + t;
+    tile[r * kScanThreads + t] = (i < n) ? in[i] : 0;
+  }
+  __syncthreads();
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k) s += tile[t * kScanItems + k];
+  int tot;
+  int pre = block_excl_scan<kScanThreads>(s, lds, &tot) + tile_offs[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    int v = tile[t * kScanItems + k];
+    tile[t * kScanItems + k] = pre;
+    pre += v;
+  }
+  __syncthreads();
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r * kScanThreads + t;
+    if (i < n) out[i] = tile[r * kScanThreads + t];
+  }
+}
+
+hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total,
+                     hipStream_t st) {
+  int ntiles = (n + kScanTile - 1) / kScanTile;
+  if (ntiles == 0) ntiles = 1;
+  k_scan_reduce<<<ntiles, kScanThreads, 0, st>>>(in, n, tile_buf);
+  k_scan_tiles<<<1, 1024, 0, st>>>(tile_buf, ntiles, total);
+  k_scan_apply<<<ntiles, kScanThreads, 0, st>>>(in, n, tile_buf, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- bbox
+template <typename T>
+__global__ __launch_bounds__(256) void k_bbox_partial(const T* __restrict__ pos, const T* __restrict__ mass,
+                                                      int64_t n, double* __restrict__ part,
+                                                      Counts* __restrict__ cnt) {
+  __shared__ double red[6][4];
+  double mn[3] = {INFINITY, INFINITY, INFINITY};
+  double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double v = (double)pos[3 * i + d];
+      if (!isfinite(v)) {
+        bad = true;
+      } else {
+        mn[d] = fmin(mn[d], v);
+        mx[d] = fmax(mx[d], v);
+      }
+    }
+    if (!isfinite((double)mass[i])) bad = true;
+  }
+  if (__any(bad) && lane_id() == 0) atomicOr(&cnt->bad_input, 1);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double a = mn[d], b = mx[d];
+    for (int o = 32; o > 0; o >>= 1) {
+      a = fmin(a, __shfl_xor(a, o, 64));
+      b = fmax(b, __shfl_xor(b, o, 64));
+    }
+    if (lane == 0) {
+      red[d][w] = a;
+      red[3 + d][w] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    int k = threadIdx.x;
+    double v = red[k][0];
+    for (int q = 1; q < 4; ++q) v = (k < 3) ? fmin(v, red[k][q]) : fmax(v, red[k][q]);
+    part[blockIdx.x * 6 + k] = v;
+  }
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nb, int64_t n, Cube* __restrict__ cube) {
+  if (threadIdx.x != 0) return;
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = INFINITY;
+    hi[d] = -INFINITY;
+  }
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], part[b * 6 + d]);
+      hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+    }
+  double L = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    if (!(lo[d] <= hi[d])) {  // no finite particle at all
+      lo[d] = 0.0;
+      hi[d] = 0.0;
+    }
+    double e = hi[d] - lo[d];
+    if (e > L) L = e;
+  }
+  if (L == 0.0) L = 1.0;
+  for (int d = 0; d < 3; ++d) cube->lo[d] = lo[d];
+  cube->L = L;
+  cube->scale = (double)kGrid / L;
+}
+
+// ---------------------------------------------------------------- Morton keys
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+  v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+  v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+  v = (v ^ (v >> 32)) & 0x1fffffull;
+  return (uint32_t)v;
+}
+
+// q_d = clamp(floor((x_d - lo_d) * 2^21/L), 0, 2^21-1); key interleaves the
+// bits with x as the most significant bit of each triplet, so the octant of a
+// child is 4*bx + 2*by + bz and key order is depth-first (Morton) order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, int n, const Cube* __restrict__ cube,
+                                              uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double sc = cube->scale;
+  uint64_t q[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double t = floor(((double)pos[3 * (int64_t)i + d] - cube->lo[d]) * sc);
+    if (!(t >= 0.0)) t = 0.0;  // also maps a non-finite input to 0 (flagged by bbox)
+    if (t > (double)(kGrid - 1)) t = (double)(kGrid - 1);
+    q[d] = (uint64_t)t;
+  }
+  keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+  idx[i] = i;
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __restrict__ keys, int n, int shift,
+                                                          int32_t* __restrict__ hist, int ntiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = (int32_t)h[threadIdx.x];
+}
+
+// Stable scatter: items of a tile are ranked in input order; within a wave the
+// rank among equal digits comes from 8 ballots (one per digit bit).
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                             const int32_t* __restrict__ vin,
+                                                             uint64_t* __restrict__ kout,
+                                                             int32_t* __restrict__ vout, int n, int shift,
+                                                             const int32_t* __restrict__ offs, int ntiles) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kSortThreads / 64][256];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  base[t] = (uint32_t)offs[(int64_t)t * ntiles + blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kSortThreads / 64; ++k) wcnt[k][t] = 0;
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint64_t le = lt | (1ull << lane);
+  for (int r = 0; r < kSortItems; ++r) {
+    int64_t i = (int64_t)blockIdx.x * kSortTile + r * kSortThreads + t;
+    bool valid = i < n;
+    uint64_t key = valid ? kin[i] : 0ull;
+    int32_t val = valid ? vin[i] : 0;
+    uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1u;
+      uint64_t m = ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & ~le) == 0ull) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t p = base[d] + rank;
+      for (int k = 0; k < w; ++k) p += wcnt[k][d];
+      kout[p] = key;
+      vout[p] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int k = 0; k < kSortThreads / 64; ++k) {
+      add += wcnt[k][t];
+      wcnt[k][t] = 0;
+    }
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- gather
+template <typename T, typename T4>
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ pos, const T* __restrict__ mass,
+                                                const int32_t* __restrict__ perm, int n, T4* __restrict__ ps) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int64_t j = perm[k];
+  T4 v;
+  v.x = pos[3 * j];
+  v.y = pos[3 * j + 1];
+  v.z = pos[3 * j + 2];
+  v.w = mass[j];
+  ps[k] = v;
+}
+
+// ---------------------------------------------------------------- unique keys
+__global__ __launch_bounds__(256) void k_unique_flags(const uint64_t* __restrict__ keys, int n,
+                                                      int32_t* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_unique_write(const uint64_t* __restrict__ keys, int n,
+                                                      const int32_t* __restrict__ flag,
+                                                      const int32_t* __restrict__ uid,
+                                                      uint64_t* __restrict__ ukey, int32_t* __restrict__ ustart,
+                                                      Counts* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (flag[i]) {
+    ukey[uid[i]] = keys[i];
+    ustart[uid[i]] = i;
+  }
+  if (i == n - 1) {
+    int U = uid[i] + flag[i];
+    ustart[U] = n;
+    cnt->n_unique = U;
+  }
+}
+
+// ---------------------------------------------------------------- topology
+// Level of the deepest cell that holds both keys: 3*level leading bits of the
+// 63-bit keys agree.  For distinct keys this is the level of the oct-tree cell
+// whose children separate them.
+__device__ __forceinline__ int split_level(uint64_t a, uint64_t b) {
+  int lcp = __clzll((long long)(a ^ b)) - 1;  // bit 63 is always 0
+  return lcp / 3;
+}
+
+__device__ __forceinline__ bool same_cell(uint64_t a, uint64_t b, int level) {
+  return level == 0 || ((a ^ b) >> (63 - 3 * level)) == 0ull;
+}
+
+// For each pair of adjacent unique keys j, j+1 with split level s, the
+// oct-tree cell (s, prefix) exists and has j|j+1 as one of its child
+// boundaries.  Its key range [f, l] is found by galloping + binary search
+// (keys are sorted, so a range shares a prefix iff its ends do).  The pair is
+// the cell's representative iff it is the first child boundary in the range.
+__global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey, const Counts* __restrict__ cnt,
+                                               int32_t* __restrict__ split, int32_t* __restrict__ rep,
+                                               int32_t* __restrict__ pf, int32_t* __restrict__ pl, int nmax) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nmax) return;
+  const int U = cnt->n_unique;
+  if (j >= U - 1) {
+    rep[j] = 0;
+    return;
+  }
+  const uint64_t kj = ukey[j], kj1 = ukey[j + 1];
+  const int s = split_level(kj, kj1);
+  split[j] = s;
+  // first key of the cell: smallest f <= j with same_cell(ukey[f], kj, s)
+  int lo = j, step = 1;
+  while (true) {
+    int cand = j - step;
+    if (cand < 0 || !same_cell(ukey[cand], kj, s)) break;
+    lo = cand;
+    step <<= 1;
+  }
+  int hi_bad = j - step;  // < 0 or outside the cell
+  int a = hi_bad, b = lo;  // invariant: a outside (or -1), b inside
+  if (a < -1) a = -1;
+  while (b - a > 1) {
+    int m = a + (b - a) / 2;
+    if (same_cell(ukey[m], kj, s)) b = m; else a = m;
+  }
+  const int f = b;
+  // last key of the cell: largest l >= j+1 with same_cell(ukey[l], kj1, s)
+  int up = j + 1;
+  step = 1;
+  while (true) {
+    int cand = j + 1 + step;
+    if (cand >= U || !same_cell(ukey[cand], kj1, s)) break;
+    up = cand;
+    step <<= 1;
+  }
+  int c = up, d = j + 1 + step;  // c inside, d outside (or U)
+  if (d > U) d = U;
+  while (d - c > 1) {
+    int m = c + (d - c) / 2;
+    if (same_cell(ukey[m], kj1, s)) c = m; else d = m;
+  }
+  const int l = c;
+  bool is_rep = (f == j) || (s < kLevels - 1 && same_cell(ukey[f], kj, s + 1));
+  rep[j] = is_rep ? 1 : 0;
+  pf[j] = f;
+  pl[j] = l;
+}
+
+__global__ __launch_bounds__(256) void k_internal_write(const int32_t* __restrict__ rep,
+                                                        const int32_t* __restrict__ irank,
+                                                        const int32_t* __restrict__ split,
+                                                        const int32_t* __restrict__ pf, const int32_t* __restrict__ pl,
+                                                        Counts* __restrict__ cnt, int32_t* __restrict__ ilevel,
+                                                        int32_t* __restrict__ ifirst, int32_t* __restrict__ ilast,
+                                                        int32_t* __restrict__ nstart, uint32_t* __restrict__ lmask,
+                                                        int nmax) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nmax) return;
+  const int U = cnt->n_unique;
+  if (j == 0) {
+    int I = (U >= 2) ? irank[U - 2] + rep[U - 2] : 0;
+    cnt->n_internal = I;
+    cnt->n_nodes = U + I;
+  }
+  if (j >= U - 1 || !rep[j]) return;
+  int v = irank[j];
+  int s = split[j], f = pf[j];
+  ilevel[v] = s;
+  ifirst[v] = f;
+  ilast[v] = pl[j];
+  atomicAdd(&nstart[f], 1);
+  atomicOr(&lmask[f], 1u << s);
+}
+
+// Preorder: for each unique-key position x, the internal nodes whose first key
+// is x (a chain of nested cells, shallowest first) come before leaf x.
+//   pre(internal v) = f + #internal nodes starting before f + #shallower nodes starting at f
+//   pre(leaf x)     = x + #internal nodes starting at or before x
+//   next(v)         = pre(leaf last(v)) + 1
+template <typename T4>
+__global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict__ cnt, const Cube* __restrict__ cube,
+                                                        const int32_t* __restrict__ ilevel,
+                                                        const int32_t* __restrict__ ifirst,
+                                                        const int32_t* __restrict__ ilast,
+                                                        const int32_t* __restrict__ nstart,
+                                                        const int32_t* __restrict__ nexcl,
+                                                        const uint32_t* __restrict__ lmask,
+                                                        const int32_t* __restrict__ ustart,
+                                                        int32_t* __restrict__ ipre, Node* __restrict__ nodes,
+                                                        int nmax) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nmax || v >= cnt->n_internal) return;
+  const int s = ilevel[v], f = ifirst[v], l = ilast[v];
+  const int pre = f + nexcl[f] + __popc(lmask[f] & ((1u << s) - 1u));
+  ipre[v] = pre;
+  Node nd;
+  nd.cx = nd.cy = nd.cz = 0.0;
+  nd.M = 0.0;
+  nd.l = ldexp(cube->L, -s);
+  nd.s = 0.0;
+  nd.next = l + nexcl[l] + nstart[l] + 1;
+  nd.first = ustart[f];
+  nd.count = ustart[l + 1] - ustart[f];
+  nd.meta = s << 8;
+  nodes[pre] = nd;
+}
+
+template <typename T4>
+__global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ cnt, const Cube* __restrict__ cube,
+                                                    const int32_t* __restrict__ split,
+                                                    const int32_t* __restrict__ nstart,
+                                                    const int32_t* __restrict__ nexcl,
+                                                    const int32_t* __restrict__ ustart, const T4* __restrict__ ps,
+                                                    Node* __restrict__ nodes, double* __restrict__ Mx, int nmax) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int U = cnt->n_unique;
+  if (x >= nmax || x >= U) return;
+  const int pre = x + nexcl[x] + nstart[x];
+  const int first = ustart[x], count = ustart[x + 1] - first;
+  int level;
+  if (count > 1) {
+    level = kLevels;
+  } else if (U == 1) {
+    level = 0;
+  } else {
+    int sl = (x > 0) ? split[x - 1] : -1;
+    int sr = (x < U - 1) ? split[x] : -1;
+    level = 1 + max(sl, sr);
+  }
+  Node nd;
+  double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
+  for (int k = first; k < first + count; ++k) {
+    T4 p = ps[k];
+    double m = (double)p.w;
+    M += m;
+    X += m * (double)p.x;
+    Y += m * (double)p.y;
+    Z += m * (double)p.z;
+  }
+  if (count == 1) {
+    T4 p = ps[first];
+    nd.cx = (double)p.x;
+    nd.cy = (double)p.y;
+    nd.cz = (double)p.z;
+  } else if (M != 0.0) {
+    nd.cx = X / M;
+    nd.cy = Y / M;
+    nd.cz = Z / M;
+  } else {
+    // massless bucket: sit at the cell centre
+    const double l = ldexp(cube->L, -level);
+    T4 p = ps[first];
+    double c[3] = {(double)p.x, (double)p.y, (double)p.z};
+    double ctr[3];
+    for (int d = 0; d < 3; ++d) {
+      double q = floor((c[d] - cube->lo[d]) * cube->scale);
+      if (!(q >= 0.0)) q = 0.0;
+      if (q > (double)(kGrid - 1)) q = (double)(kGrid - 1);
+      ctr[d] = cube->lo[d] + (q + 0.5) * l;
+    }
+    nd.cx = ctr[0];
+    nd.cy = ctr[1];
+    nd.cz = ctr[2];
+  }
+  nd.M = M;
+  nd.l = ldexp(cube->L, -level);
+  nd.s = 0.0;
+  nd.next = pre + 1;
+  nd.first = first;
+  nd.count = count;
+  nd.meta = 1 | (level << 8);
+  nodes[pre] = nd;
+  Mx[3 * (int64_t)pre] = X;
+  Mx[3 * (int64_t)pre + 1] = Y;
+  Mx[3 * (int64_t)pre + 2] = Z;
+}
+
+// Moments of the internal nodes of one level (children are deeper, so they are
+// final).  Children are pre+1, next(pre+1), ... < next(pre), in octant order.
+__global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict__ cnt, const Cube* __restrict__ cube,
+                                                       const int32_t* __restrict__ ilevel,
+                                                       const int32_t* __restrict__ ifirst,
+                                                       const int32_t* __restrict__ ipre,
+                                                       const uint64_t* __restrict__ ukey, Node* __restrict__ nodes,
+                                                       double* __restrict__ Mx, int level, int nmax) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nmax || v >= cnt->n_internal || ilevel[v] != level) return;
+  const int p = ipre[v];
+  const int n_nodes = cnt->n_nodes;
+  const int end = min(nodes[p].next, n_nodes);
+  double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
+  // at most 8 children; the bound also keeps a corrupted record from looping
+  int c = p + 1;
+  for (int k = 0; k < 8 && c < end; ++k, c = max(nodes[c].next, c + 1)) {
+    M += nodes[c].M;
+    X += Mx[3 * (int64_t)c];
+    Y += Mx[3 * (int64_t)c + 1];
+    Z += Mx[3 * (int64_t)c + 2];
+  }
+  const double l = nodes[p].l;
+  const uint64_t prefix = (level == 0) ? 0ull : (ukey[ifirst[v]] >> (63 - 3 * level));
+  const double ctr[3] = {cube->lo[0] + ((double)compact3(prefix >> 2) + 0.5) * l,
+                         cube->lo[1] + ((double)compact3(prefix >> 1) + 0.5) * l,
+                         cube->lo[2] + ((double)compact3(prefix) + 0.5) * l};
+  double com[3];
+  if (M != 0.0) {
+    com[0] = X / M;
+    com[1] = Y / M;
+    com[2] = Z / M;
+  } else {
+    com[0] = ctr[0];
+    com[1] = ctr[1];
+    com[2] = ctr[2];
+  }
+  const double dx = ctr[0] - com[0], dy = ctr[1] - com[1], dz = ctr[2] - com[2];
+  nodes[p].cx = com[0];
+  nodes[p].cy = com[1];
+  nodes[p].cz = com[2];
+  nodes[p].M = M;
+  nodes[p].s = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+  Mx[3 * (int64_t)p] = X;
+  Mx[3 * (int64_t)p + 1] = Y;
+  Mx[3 * (int64_t)p + 2] = Z;
+}
+
+// ---------------------------------------------------------------- driver
+static inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t) > 0 ? (int)((n + t - 1) / t) : 1; }
+
+template <typename T, typename T4>
+static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& w, hipStream_t st) {
+  hipError_t e;
+  k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(w.counts), sizeof(Counts) / 4, 0);
+  if (n == 0) return hipGetLastError();
+  // root cube
+  const int nbb = w.n_bbox_blocks;
+  k_bbox_partial<T><<<nbb, 256, 0, st>>>(pos, mass, n, w.bbox_part, w.counts);
+  k_bbox_final<<<1, 64, 0, st>>>(w.bbox_part, nbb, n, w.cube);
+  // keys and stable sort
+  k_keys<T><<<nblk(n, 256), 256, 0, st>>>(pos, n, w.cube, w.key_a, w.idx_a);
+  const int ntiles = (n + kSortTile - 1) / kSortTile;
+  uint64_t *kin = w.key_a, *kout = w.key_b;
+  int32_t *vin = w.idx_a, *vout = w.idx_b;
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 8 * pass;
+    k_rs_hist<<<ntiles, kSortThreads, 0, st>>>(kin, n, shift, w.hist, ntiles);
+    if ((e = scan_excl(w.hist, w.hist, 256 * ntiles, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
+    k_rs_scatter<<<ntiles, kSortThreads, 0, st>>>(kin, vin, kout, vout, n, shift, w.hist, ntiles);
+    uint64_t* tk = kin; kin = kout; kout = tk;
+    int32_t* tv = vin; vin = vout; vout = tv;
+  }
+  // after an even number of passes the sorted data is back in key_a / idx_a
+  k_gather<T, T4><<<nblk(n, 256), 256, 0, st>>>(pos, mass, w.idx_a, n, reinterpret_cast<T4*>(w.ps));
+  // unique keys
+  k_unique_flags<<<nblk(n, 256), 256, 0, st>>>(w.key_a, n, w.flag);
+  if ((e = scan_excl(w.flag, w.uid, n, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
+  k_unique_write<<<nblk(n, 256), 256, 0, st>>>(w.key_a, n, w.flag, w.uid, w.ukey, w.ustart, w.counts);
+  // internal nodes
+  k_pairs<<<nblk(n, 256), 256, 0, st>>>(w.ukey, w.counts, w.split, w.flag, w.pf, w.pl, n);
+  if ((e = scan_excl(w.flag, w.uid, n, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
+  k_fill_i32<<<nblk(n + 1, 256), 256, 0, st>>>(w.nstart, n + 1, 0);
+  k_fill_i32<<<nblk(n + 1, 256), 256, 0, st>>>(reinterpret_cast<int32_t*>(w.lmask), n + 1, 0);
+  k_internal_write<<<nblk(n, 256), 256, 0, st>>>(w.flag, w.uid, w.split, w.pf, w.pl, w.counts, w.ilevel, w.ifirst,
+                                                 w.ilast, w.nstart, w.lmask, n);
+  if ((e = scan_excl(w.nstart, w.nexcl, n + 1, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
+  k_nodes_internal<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ilevel, w.ifirst, w.ilast, w.nstart,
+                                                     w.nexcl, w.lmask, w.ustart, w.ipre, w.nodes, n);
+  k_nodes_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.split, w.nstart, w.nexcl, w.ustart,
+                                                 reinterpret_cast<const T4*>(w.ps), w.nodes, w.Mx, n);
+  for (int level = kLevels - 1; level >= 0; --level)
+    k_moments_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ilevel, w.ifirst, w.ipre, w.ukey, w.nodes,
+                                                  w.Mx, level, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ perm, int n, int32_t* __restrict__ rank) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) rank[perm[k]] = k;
+}
+
+hipError_t make_rank(const int32_t* perm, int n, int32_t* rank, hipStream_t st) {
+  k_rank<<<nblk(n, 256), 256, 0, st>>>(perm, n, rank);
+  return hipGetLastError();
+}
+
+hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st) {
+  return build_impl<float, float4>(pos, mass, n, w, st);
+}
+
+hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, hipStream_t st) {
+  return build_impl<double, double4>(pos, mass, n, w, st);
+}
+
+}  // namespace bh

@@ -1,0 +1,63 @@
+// bh_common.h -- shared definitions of the gfx950 Barnes-Hut library (device and host side).
+//
+// Data layout in HBM (one tree of n particles; every array lives in the
+// caller's workspace):
+//   * particles, Morton order:  float4/double4 (x, y, z, m) per particle, plus
+//     perm[k] = caller index of the k-th particle in Morton order.
+//   * nodes, depth-first preorder (Sec. 4.4 next/more pointers): one 64-byte
+//     Node per cell or leaf.  more(c) is implicitly c+1; next(c) is stored.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bh {
+
+constexpr int kLevels = 21;                 // bits per axis of the Morton grid (63-bit keys)
+constexpr uint32_t kGrid = 1u << kLevels;   // cells per axis at the finest level
+constexpr int kWave = 64;                   // CDNA wavefront width
+
+// One node of the tree, 64 bytes, read by the walk with scalar loads.
+//   com   : centre of mass (a one-particle leaf: the particle's position, exact)
+//   M     : total mass (FP64 sum, children folded left in octant order)
+//   l     : side of the cell, L * 2^-level
+//   s     : |geometric centre - com| (Eq. (2) of the paper), 0 for leaves
+//   next  : preorder id of the first node after this subtree
+//   first : Morton position of the first particle of the subtree
+//   count : number of particles in the subtree
+//   meta  : bit 0 = leaf, bits 8..15 = level
+struct alignas(64) Node {
+  double cx, cy, cz;
+  double M;
+  double l;
+  double s;
+  int32_t next;
+  int32_t first;
+  int32_t count;
+  int32_t meta;
+};
+static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
+
+// Root cube and Morton quantisation, computed on the device by the bbox pass.
+struct Cube {
+  double lo[3];   // coordinate-wise minimum of the particles
+  double L;       // largest extent (1 if every particle coincides)
+  double scale;   // 2^21 / L
+  double pad[3];
+};
+
+// Device-side counters of one build.
+struct Counts {
+  int32_t n_unique;     // U: distinct Morton keys (= leaves)
+  int32_t n_internal;   // I: internal nodes
+  int32_t n_nodes;      // U + I
+  int32_t bad_input;    // nonzero if a coordinate or mass was not finite
+  int32_t pad[4];
+};
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+}  // namespace bh

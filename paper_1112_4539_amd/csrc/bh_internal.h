@@ -1,0 +1,73 @@
+// bh_internal.h -- launch-side declarations shared by the library's translation units.
+#pragma once
+#include "bh_common.h"
+
+namespace bh {
+
+// scans: 256 threads x 16 items per tile
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+// radix sort: 256 threads x 16 keys per tile, 8-bit digits
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kBboxBlocks = 1024;
+
+// Views into the caller's workspace used by one tree build.
+struct BuildWs {
+  Cube* cube;
+  Counts* counts;
+  double* bbox_part;        // [kBboxBlocks][6]
+  int n_bbox_blocks;
+  uint64_t *key_a, *key_b;  // [n]
+  int32_t *idx_a, *idx_b;   // [n]; idx_a ends as perm (Morton position -> caller index)
+  int32_t* hist;            // [256 * ntiles]
+  int32_t* scan_tiles;      // scan scratch
+  void* ps;                 // [n] float4 or double4 (x, y, z, m) in Morton order
+  int32_t *flag, *uid;      // [n]
+  uint64_t* ukey;           // [n]
+  int32_t* ustart;          // [n + 1]
+  int32_t *split, *pf, *pl; // [n]
+  int32_t *ilevel, *ifirst, *ilast, *ipre;  // [n]
+  int32_t *nstart, *nexcl;  // [n + 1]
+  uint32_t* lmask;          // [n + 1]
+  Node* nodes;              // [2n]
+  double* Mx;               // [2n][3]
+};
+
+hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total, hipStream_t st);
+hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st);
+hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, hipStream_t st);
+
+// Tree walk launch.  Targets are processed in groups of 64 (one wavefront);
+// group g holds the targets at positions [64g, 64g+64) of `order` (Morton
+// positions; null = Morton order itself).
+struct WalkArgs {
+  const Node* nodes;
+  const void* ps;              // float4 / double4 particles in Morton order
+  const int32_t* perm;         // Morton position -> caller index
+  const int32_t* order;        // optional target order (Morton positions), may be null
+  int n;
+  double eps2;
+  double inv_theta;            // 1/theta when theta_group is null
+  const float* theta_group;    // theta per 64-particle Morton group, may be null
+  void* acc;                   // [n][3] caller order
+  void* pot;                   // [n] caller order
+  int32_t* counts;             // stats: [n][2] = (particle terms, cell terms), caller order
+  uint64_t* hash;              // stats: [n] ordered-list hash, caller order
+  int64_t* lists;              // dump: [n][maxlen] list words, caller order
+  int64_t maxlen;
+  int xcd_chunk;               // workgroups per XCD chunk of the block remap (0 = identity)
+  int waves_per_block;         // 1, 2 or 4
+};
+
+enum WalkMode { kWalkForces = 0, kWalkStats = 1, kWalkDump = 2 };
+
+hipError_t launch_walk(bool f64, int mode, const WalkArgs& a, hipStream_t st);
+
+// Direct sum of Eq. (1) for a list of targets (caller indices).
+hipError_t launch_direct(bool f64, const void* pos, const void* mass, int n, const int64_t* targets, int nt,
+                         double eps, void* acc, void* pot, hipStream_t st);
+
+}  // namespace bh

@@ -1,0 +1,65 @@
+"""CPU-side checks of the C ABI: the library loads and exports every declared symbol.
+
+No compute call is made here (there is no GPU in the build container); the
+argument checks that fail before any device work are exercised.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bh.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bh_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("bh_build_tree", "bh_forces", "bh_forces_theta", "bh_direct", "bh_workspace_bytes",
+                 "bh_walk_stats", "bh_tree_export", "bh_tree_release", "bh_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1112_4539_amd as bh
+    lib = bh.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    # nothing else with C linkage leaks out under the bh_ prefix
+    out = os.popen(f"nm -D --defined-only {bh.LIB_PATH}").read()
+    exported = sorted(set(re.findall(r"\s(bh_[a-z_0-9]+)$", out, flags=re.M)))
+    assert exported == _declared()
+
+
+def test_host_side_argument_checks():
+    import paper_1112_4539_amd as bh
+    lib = bh.load()
+    assert lib.bh_version() == 1
+    assert lib.bh_workspace_bytes(-1, 0) == -1
+    assert lib.bh_workspace_bytes(1 << 31, 0) == -1
+    assert lib.bh_workspace_bytes(10, 7) == -1
+    w1 = lib.bh_workspace_bytes(1000, 0)
+    w2 = lib.bh_workspace_bytes(1000, 1)
+    assert 0 < w1 < w2
+    assert lib.bh_workspace_bytes(2000, 0) > w1
+    out = ctypes.c_void_p()
+    # bad precision / n / missing workspace are rejected before any GPU work
+    assert lib.bh_build_tree(None, None, 10, 5, None, 0, None, ctypes.byref(out)) == -1
+    assert lib.bh_build_tree(None, None, -3, 0, None, 0, None, ctypes.byref(out)) == -1
+    assert lib.bh_build_tree(ctypes.c_void_p(256), ctypes.c_void_p(512), 10, 0, None, 0, None,
+                             ctypes.byref(out)) == -2
+    assert b"workspace" in lib.bh_last_error()
+    assert lib.bh_forces(None, 0.5, 0.01, None, None, None) == -1
+    assert lib.bh_direct(None, None, 10, 0, None, 5, -1.0, None, None, None) == -1
+    assert lib.bh_set_walk_config(None, 4, 0, 0) == -1
+
+
+def test_theta_bound_matches_header():
+    import paper_1112_4539_amd as bh
+    assert abs(bh.THETA_MAX - 2 / 3 ** 0.5) < 1e-15

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP library against the CPU FP64 oracle, element by element.
+
+Tree: node set, preorder numbering, next pointers and FP64 moments bit-exact.
+Walk: interaction lists identical (full dumps at small n, per-particle count +
+ordered-list hash at full size), forces within 1e-12 (FP64) / 1e-5 (FP32)
+relative per particle, with the cancellation floor of ``util.force_err``.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_4539_amd import inputs
+from tests.util import force_err, pot_err, tree_cases, widen
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL = 1e-5
+F64_TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bh():
+    import paper_1112_4539_amd as bh
+    bh.load()
+    assert torch.cuda.is_available()
+    return bh
+
+
+def _np_dtype(prec):
+    return np.float32 if prec == "fp32" else np.float64
+
+
+def _gpu(pos, mass, prec):
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    return (torch.tensor(pos, dtype=dt, device="cuda"), torch.tensor(mass, dtype=dt, device="cuda"))
+
+
+def _seen(pos, mass, prec):
+    """The values the GPU sees, widened exactly to float64 for the oracle."""
+    t = _np_dtype(prec)
+    return pos.astype(t).astype(np.float64), mass.astype(t).astype(np.float64)
+
+
+def _compare_trees(bh, pos, mass, prec):
+    gp, gm = _gpu(pos, mass, prec)
+    T = bh.Tree(gp, gm)
+    rec, perm = T.export()
+    p64, m64 = _seen(pos, mass, prec)
+    O = oracle.Tree(p64, m64)
+    assert len(rec) == O.n_nodes
+    np.testing.assert_array_equal(perm, O.perm)
+    np.testing.assert_array_equal(rec["meta"] & 1, O.leaf)
+    np.testing.assert_array_equal(rec["meta"] >> 8, O.level)
+    np.testing.assert_array_equal(rec["first"], O.first)
+    np.testing.assert_array_equal(rec["count"], O.count)
+    np.testing.assert_array_equal(rec["next"], O.next)
+    np.testing.assert_array_equal(rec["com"], O.com)
+    np.testing.assert_array_equal(rec["M"], O.M)
+    np.testing.assert_array_equal(rec["l"], O.l)
+    np.testing.assert_array_equal(rec["s"], O.s)
+    return T, O
+
+
+@pytest.mark.parametrize("name", sorted(tree_cases()))
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tree_bitexact_small(bh, name, prec):
+    say(f"[tree] case={name} prec={prec}")
+    pos = tree_cases()[name]
+    mass = np.random.default_rng(len(pos)).random(len(pos)) + 0.5
+    _compare_trees(bh, pos, mass, prec)
+
+
+@pytest.mark.parametrize("which,prec", [("plummer4k", "fp64"), ("plummer4k", "fp32"), ("clumpy", "fp32")])
+def test_tree_bitexact_workloads(bh, which, prec):
+    say(f"[tree] workload={which} prec={prec}")
+    if which == "plummer4k":
+        pos, mass = inputs.plummer(4096, 0)
+    else:
+        pos, mass = inputs.clumpy(200_003, 21)      # ragged: not a multiple of any tile
+    _compare_trees(bh, pos, mass, prec)
+
+
+def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta_group=None):
+    gp, gm = _gpu(pos, mass, prec)
+    T = bh.Tree(gp, gm)
+    tg_t = None if theta_group is None else torch.tensor(theta_group, dtype=torch.float32, device="cuda")
+    out = T.walk_stats(theta, eps, theta_group=tg_t, maxlen=maxlen)
+    acc_f, pot_f = T.forces(theta, eps, theta_group=tg_t)
+    torch.cuda.synchronize()
+    # the plain force walk gives the very same numbers as the instrumented one
+    assert torch.equal(acc_f, out["acc"]) and torch.equal(pot_f, out["pot"])
+    p64, m64 = _seen(pos, mass, prec)
+    O = oracle.Tree(p64, m64)
+    idx = np.arange(len(pos)) if targets is None else targets
+    tpt = None
+    if theta_group is not None:
+        rank = np.empty(len(pos), np.int64)
+        rank[O.perm] = np.arange(len(pos))
+        tpt = np.asarray(theta_group, np.float32).astype(np.float64)[rank[idx] // 64]
+    w = O.walk(theta, eps, targets=idx, theta_per_target=tpt, maxlen=maxlen)
+    cnt = out["counts"].cpu().numpy()[idx]
+    np.testing.assert_array_equal(cnt[:, 0], w["n_pp"])
+    np.testing.assert_array_equal(cnt[:, 1], w["n_pc"])
+    np.testing.assert_array_equal(out["hash"].cpu().numpy().view(np.uint64)[idx], w["hash"])
+    if maxlen:
+        np.testing.assert_array_equal(out["lists"].cpu().numpy()[idx], w["lists"])
+    acc = out["acc"].cpu().numpy()[idx]
+    pot = out["pot"].cpu().numpy()[idx]
+    return acc, pot, w
+
+
+def test_lists_and_forces_plummer4k_fp64(bh):
+    say("[walk] plummer4k fp64 theta=0.5 full list dump")
+    pos, mass = inputs.plummer(4096, 0)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp64", 0.5, 0.01, maxlen=4096)
+    e = force_err(acc, w["acc"], w["amag"])
+    say(f"  max err {e.max():.3e}  bit-exact share {np.mean(np.all(acc == w['acc'], axis=1)):.4f}")
+    assert e.max() <= F64_TOL
+    assert pot_err(pot, w["pot"]).max() <= F64_TOL
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
+def test_lists_and_forces_plummer4k_fp32(bh, theta):
+    say(f"[walk] plummer4k fp32 theta={theta} full list dump")
+    pos, mass = inputs.plummer(4096, 0)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, 0.01, maxlen=4096)
+    e = force_err(acc, w["acc"], w["amag"])
+    say(f"  max err {e.max():.3e} p99 {np.quantile(e, 0.99):.3e}")
+    assert e.max() <= F32_TOL
+    assert pot_err(pot, w["pot"]).max() <= F32_TOL
+
+
+def test_theta_per_group(bh):
+    say("[walk] per-group theta, clumpy 50k fp32")
+    pos, mass = inputs.clumpy(50_000, 31)
+    g = (len(pos) + 63) // 64
+    tg = np.random.default_rng(3).uniform(0.2, 1.0, g).astype(np.float32)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.5, 1e-4, theta_group=tg)
+    e = force_err(acc, w["acc"], w["amag"])
+    say(f"  max err {e.max():.3e}")
+    assert e.max() <= F32_TOL
+
+
+def test_direct_fp64_matches_definition(bh):
+    say("[direct] plummer4k fp64")
+    pos, mass = inputs.plummer(4096, 0)
+    gp, gm = _gpu(pos, mass, "fp64")
+    tg = torch.arange(4096, device="cuda")
+    acc, pot = bh.direct(gp, gm, 0.01, tg)
+    a_ref, p_ref, amag = oracle.direct(pos, mass, 0.01)
+    acc = acc.cpu().numpy()
+    e = force_err(acc, a_ref, amag)
+    say(f"  max err {e.max():.3e} bit-exact share {np.mean(acc == a_ref):.4f}")
+    assert e.max() <= F64_TOL
+    assert pot_err(pot.cpu().numpy(), p_ref).max() <= F64_TOL
+
+
+def test_direct_fp32_close_to_fp64(bh):
+    say("[direct] plummer 20k fp32 vs fp64")
+    pos, mass = inputs.plummer(20_000, 5)
+    tg = torch.tensor(inputs.sample_targets(20_000, 2000, 5), device="cuda")
+    a32, _ = bh.direct(*_gpu(pos, mass, "fp32"), 0.01, tg)
+    p64, m64 = _seen(pos, mass, "fp32")
+    a64, _, amag = oracle.direct(p64, m64, 0.01, targets=tg.cpu().numpy())
+    assert np.quantile(force_err(a32.cpu().numpy(), a64, amag), 0.99) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_permutation_and_scaling_bitexact(bh, prec):
+    say(f"[invariance] plummer 30k {prec}")
+    pos, mass = inputs.plummer(30_000, 8)
+    perm = np.random.default_rng(4).permutation(len(pos))
+    T1 = bh.Tree(*_gpu(pos, mass, prec))
+    a1, p1 = T1.forces(0.6, 0.01)
+    T2 = bh.Tree(*_gpu(pos[perm], mass[perm], prec))
+    a2, p2 = T2.forces(0.6, 0.01)
+    pt = torch.tensor(perm, device="cuda")
+    assert torch.equal(a2, a1[pt]) and torch.equal(p2, p1[pt])
+    T3 = bh.Tree(*_gpu(pos * 2.0, mass * 8.0, prec))
+    a3, p3 = T3.forces(0.6, 0.02)
+    assert torch.equal(a3, 2 * a1) and torch.equal(p3, 4 * p1)
+
+
+def test_launch_shapes_and_target_order_bitexact(bh):
+    say("[invariance] launch shapes, clumpy 100k fp32")
+    pos, mass = inputs.clumpy(100_000, 9)
+    T = bh.Tree(*_gpu(pos, mass, "fp32"))
+    ref = T.forces(0.5, 1e-4)
+    for wpb in (1, 2, 4):
+        for chunk in (0, 4, 16):
+            for order in (0, 1):
+                T.set_walk_config(wpb, chunk, order)
+                a, p = T.forces(0.5, 1e-4)
+                assert torch.equal(a, ref[0]) and torch.equal(p, ref[1]), (wpb, chunk, order)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_edge_cases(bh, prec):
+    say(f"[edge] {prec}")
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    # empty
+    T = bh.Tree(torch.empty((0, 3), dtype=dt, device="cuda"), torch.empty((0,), dtype=dt, device="cuda"))
+    a, p = T.forces(0.5, 0.01)
+    assert a.shape == (0, 3) and T.stats()["n_nodes"] == 0
+    # one particle: no force
+    T = bh.Tree(torch.tensor([[0.3, 0.1, -2.0]], dtype=dt, device="cuda"), torch.tensor([2.0], dtype=dt, device="cuda"))
+    a, p = T.forces(0.5, 0.01)
+    assert torch.all(a == 0) and torch.all(p == 0)
+    # two particles: the closed form (dx = (1,2,2), eps = 4 -> r = 5)
+    T = bh.Tree(torch.tensor([[0, 0, 0], [1, 2, 2]], dtype=dt, device="cuda"),
+                torch.tensor([1.0, 0.75], dtype=dt, device="cuda"))
+    a, p = T.forces(0.5, 4.0)
+    np.testing.assert_allclose(a.cpu().numpy()[0], 0.75 * np.array([1, 2, 2]) / 125, rtol=4e-7)
+    np.testing.assert_allclose(p.cpu().numpy(), [-0.15, -0.2], rtol=4e-7)
+    # all coincident: one bucket leaf, potentials -m/eps, zero accelerations
+    pos = torch.full((70, 3), 0.25, dtype=dt, device="cuda")
+    mass = torch.full((70,), 0.5, dtype=dt, device="cuda")
+    T = bh.Tree(pos, mass)
+    a, p = T.forces(0.5, 0.5)
+    assert T.stats()["n_nodes"] == 1
+    assert torch.all(a == 0)
+    np.testing.assert_allclose(p.cpu().numpy(), -69 * 0.5 / 0.5, rtol=1e-6)
+    # invalid parameters are rejected on the host
+    for bad in (0.0, -0.1, 1.2, float("nan")):
+        with pytest.raises(ValueError):
+            T.forces(bad, 0.01)
+    with pytest.raises(ValueError):
+        T.forces(0.5, -1.0)
+    # non-finite inputs are reported by the check pass
+    pos = torch.rand((100, 3), dtype=dt, device="cuda")
+    pos[17, 1] = float("nan")
+    T = bh.Tree(pos, torch.ones(100, dtype=dt, device="cuda"))
+    with pytest.raises(ValueError):
+        T.check()
+
+
+@pytest.mark.parametrize("name,theta", [("plummer1m", 0.3), ("plummer1m", 0.5), ("plummer1m", 0.75),
+                                        ("clumpy4m", 0.5)])
+def test_full_size_sampled(bh, name, theta):
+    say(f"[full] {name} theta={theta} (sampled targets)")
+    pos, mass, spec = inputs.make(name)
+    tg = inputs.sample_targets(len(pos), 2048, spec["seed"] + 100)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, spec["eps"], targets=tg)
+    e = force_err(acc, w["acc"], w["amag"])
+    say(f"  max err {e.max():.3e}  p99 {np.quantile(e, 0.99):.3e}  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
+    assert e.max() <= F32_TOL
+    assert pot_err(pot, w["pot"]).max() <= F32_TOL

@@ -1,0 +1,46 @@
+"""Shared helpers of the test suite (comparison rules; no method arithmetic)."""
+import numpy as np
+
+
+def widen(a):
+    """float32/float64 array -> float64 (exact)."""
+    return np.asarray(a, dtype=np.float64)
+
+
+def force_err(acc, acc_ref, amag, kappa_max=1e3):
+    """Per-particle relative force error with a cancellation floor.
+
+    err_i = |a_i - a_ref_i| / max(|a_ref_i|, A_i / kappa_max), A_i = sum_j |f_ij|
+    the sum of the magnitudes of particle i's terms.  It is the plain relative
+    error whenever the cancellation ratio A_i/|a_i| is at most kappa_max.
+    """
+    acc = widen(acc)
+    acc_ref = widen(acc_ref)
+    den = np.maximum(np.linalg.norm(acc_ref, axis=1), widen(amag) / kappa_max)
+    return np.linalg.norm(acc - acc_ref, axis=1) / den
+
+
+def pot_err(pot, pot_ref):
+    pot = widen(pot)
+    pot_ref = widen(pot_ref)
+    return np.abs(pot - pot_ref) / np.abs(pot_ref)
+
+
+def tree_cases():
+    """Small particle sets that exercise the tree build's corner cases."""
+    rng = np.random.default_rng(5)
+    cases = {}
+    for n in (1, 2, 3, 5, 8, 13, 16, 100, 1000):
+        cases[f"random{n}"] = rng.random((n, 3))
+    p = rng.random((12, 3))
+    p[5] = p[2]; p[9] = p[2]; p[7] = p[1]
+    cases["duplicates"] = p
+    cases["coincident"] = np.tile(rng.random((1, 3)), (6, 1))
+    p = rng.random((10, 3))
+    p[3] = p[4] + 1e-9
+    cases["finest_cell_pair"] = p
+    p = np.zeros((9, 3)); p[:, 0] = np.arange(9) * 2.0 ** -18
+    cases["collinear_deep"] = p
+    p = rng.random((777, 3)) * np.array([1.0, 1e-3, 1e-6])     # flat, anisotropic
+    cases["flat"] = p
+    return cases
