@@ -111,14 +111,17 @@ BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double ep
  * with source j (caller index), w = c<<1|1 for a cell term with node c
  * (depth-first preorder id).  If lists != NULL it also writes the first maxlen
  * words of each list to lists [n][maxlen] (entries past the list are left as
- * they were). */
+ * they were).  If group_steps != NULL it receives, per group of 64 targets of
+ * the walk (ceil(n/64) int32), the number of nodes the group's wavefront
+ * visited: sum(counts) / (64 * sum(group_steps)) is the share of useful lanes. */
 BH_API int bh_walk_stats(const bh_tree *t, double theta, const float *theta_group, double eps, void *acc,
                   void *pot, int32_t *counts, uint64_t *hash, int64_t *lists, int64_t maxlen,
-                  void *stream);
+                  int32_t *group_steps, void *stream);
 
 /* Copy the tree out for inspection: nodes (device, n_nodes records of 64
  * bytes: double com[3], M, l, s; int32 next, first, count, meta with bit 0 =
- * leaf and bits 8-15 = level) and perm [n] (device int32: Morton position ->
+ * leaf, bit 1 = leaf of several coincident-key particles, bits 8-15 = level)
+ * and perm [n] (device int32: Morton position ->
  * caller index).  Either pointer may be NULL.  Synchronises the stream. */
 BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *stream);
 

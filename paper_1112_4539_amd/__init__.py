@@ -47,7 +47,7 @@ def load():
         "bh_tree_stats": ([P, P, P, P, P], i32),
         "bh_forces": ([P, d, d, P, P, P], i32),
         "bh_forces_theta": ([P, P, d, P, P, P], i32),
-        "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P], i32),
+        "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P, P], i32),
         "bh_tree_export": ([P, P, P, P], i32),
         "bh_set_walk_config": ([P, i32, i32, i32], i32),
         "bh_set_timing": ([P, i32], i32),
@@ -197,17 +197,20 @@ class Tree:
         return acc, pot
 
     def walk_stats(self, theta=0.5, eps=0.0, theta_group=None, maxlen=0):
-        """Forces plus per-particle (particle terms, cell terms), list hash and optional list dump."""
+        """Forces plus per-particle (particle terms, cell terms), list hash, nodes visited per
+        64-target group, and an optional list dump."""
         acc, pot = self._outs(None, None)
         counts = torch.empty((self.n, 2), dtype=torch.int32, device=self.device)
         hsh = torch.empty((self.n,), dtype=torch.int64, device=self.device)
+        steps = torch.zeros(((self.n + 63) // 64,), dtype=torch.int32, device=self.device)
         lists = None
         if maxlen > 0:
             lists = torch.full((self.n, maxlen), -1, dtype=torch.int64, device=self.device)
         tg = self._theta_group(theta_group)
         _check(load().bh_walk_stats(self._h, float(theta), _ptr(tg), float(eps), _ptr(acc), _ptr(pot),
-                                    _ptr(counts), _ptr(hsh), _ptr(lists), int(maxlen), _stream(self.device)))
-        out = dict(acc=acc, pot=pot, counts=counts, hash=hsh)
+                                    _ptr(counts), _ptr(hsh), _ptr(lists), int(maxlen), _ptr(steps),
+                                    _stream(self.device)))
+        out = dict(acc=acc, pot=pot, counts=counts, hash=hsh, group_steps=steps)
         if lists is not None:
             out["lists"] = lists
         return out

@@ -14,18 +14,18 @@ LIB = os.path.join(HERE, "libbh.so")
 SOURCES = ["bh_build.hip", "bh_walk.hip", "bh_direct.hip", "bh_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950:xnack-", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall",
 ]
+# The walk prefetches the two possible successor nodes at the top of each
+# step; machine sinking would move those loads down next to their use.
+EXTRA = {"bh_walk.hip": ["-mllvm", "-disable-machine-sink"]}
+BUILD_DIR = os.path.join(HERE, "_build")
 
 
-def build(verbose=False):
-    """Compile the library in-tree; returns the path of libbh.so."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -34,7 +34,19 @@ def build(verbose=False):
     if msgs:
         print("\n".join(msgs), flush=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed with status {r.returncode}")
+        raise RuntimeError(f"hipcc failed with status {r.returncode}: {' '.join(cmd)}")
+
+
+def build(verbose=False):
+    """Compile the library in-tree (one object per source, then link); returns the path of libbh.so."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+        _run([HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", "-o", obj, os.path.join(CSRC, src)], verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950:xnack-", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
     return LIB
 

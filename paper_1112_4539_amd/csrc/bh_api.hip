@@ -94,6 +94,7 @@ size_t layout(int64_t n, int prec, char* base, bh::BuildWs* w, int32_t** rank) {
   t.lmask = reinterpret_cast<uint32_t*>(take(4 * (N + 1)));
   t.nodes = reinterpret_cast<bh::Node*>(take(sizeof(bh::Node) * nodes));
   t.Mx = reinterpret_cast<double*>(take(24 * nodes));
+  t.wnodes = reinterpret_cast<bh::WalkNode*>(take(sizeof(bh::WalkNode) * nodes));
   int32_t* r = reinterpret_cast<int32_t*>(take(4 * N));
   if (w) *w = t;
   if (rank) *rank = r;
@@ -118,7 +119,8 @@ int sync_counts(const bh_tree* t, hipStream_t st, bh::Counts* c) {
 }
 
 int run_walk(const bh_tree* t, double theta, const float* theta_group, double eps, void* acc, void* pot,
-             int mode, int32_t* counts, uint64_t* hash, int64_t* lists, int64_t maxlen, hipStream_t st) {
+             int mode, int32_t* counts, uint64_t* hash, int64_t* lists, int64_t maxlen, int32_t* group_steps,
+             hipStream_t st) {
   if (!t) return fail(BH_EINVAL, "null tree");
   if (!theta_group) {
     int rc = check_theta_eps(theta, eps);
@@ -134,8 +136,13 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
     return fail(BH_EINVAL, "counts/hash must be non-null aligned device arrays");
   if (mode == bh::kWalkDump && (!lists || maxlen <= 0 || !aligned(lists, 8)))
     return fail(BH_EINVAL, "lists must be a non-null aligned device array with maxlen > 0");
+  if (!theta_group) {
+    hipError_t e = bh::launch_mac_size(t->w.nodes, t->w.counts, (int)(2 * t->n), 1.0 / theta, t->w.wnodes, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the opening-size pass");
+  }
   bh::WalkArgs a{};
   a.nodes = t->w.nodes;
+  a.wnodes = t->w.wnodes;
   a.ps = t->w.ps;
   a.perm = t->w.idx_a;
   a.order = t->target_order == 1 ? t->rank : nullptr;
@@ -149,6 +156,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.hash = hash;
   a.lists = lists;
   a.maxlen = maxlen;
+  a.group_steps = group_steps;
   a.xcd_chunk = t->xcd_chunk;
   a.waves_per_block = t->waves_per_block;
   bh_tree* mt = const_cast<bh_tree*>(t);
@@ -234,19 +242,21 @@ int bh_tree_stats(const bh_tree* t, void* stream, int64_t* n_nodes, int64_t* n_l
 
 int bh_forces(const bh_tree* t, double theta, double eps, void* acc, void* pot, void* stream) {
   return run_walk(t, theta, nullptr, eps, acc, pot, bh::kWalkForces, nullptr, nullptr, nullptr, 0,
-                  static_cast<hipStream_t>(stream));
+                  nullptr, static_cast<hipStream_t>(stream));
 }
 
 int bh_forces_theta(const bh_tree* t, const float* theta_group, double eps, void* acc, void* pot, void* stream) {
   if (!theta_group) return fail(BH_EINVAL, "theta_group must not be null");
   return run_walk(t, 0.0, theta_group, eps, acc, pot, bh::kWalkForces, nullptr, nullptr, nullptr, 0,
-                  static_cast<hipStream_t>(stream));
+                  nullptr, static_cast<hipStream_t>(stream));
 }
 
 int bh_walk_stats(const bh_tree* t, double theta, const float* theta_group, double eps, void* acc, void* pot,
-                  int32_t* counts, uint64_t* hash, int64_t* lists, int64_t maxlen, void* stream) {
+                  int32_t* counts, uint64_t* hash, int64_t* lists, int64_t maxlen, int32_t* group_steps,
+                  void* stream) {
+  if (group_steps && !aligned(group_steps, 4)) return fail(BH_EINVAL, "group_steps must be 4-byte aligned");
   return run_walk(t, theta, theta_group, eps, acc, pot, lists ? bh::kWalkDump : bh::kWalkStats, counts, hash,
-                  lists, maxlen, static_cast<hipStream_t>(stream));
+                  lists, maxlen, group_steps, static_cast<hipStream_t>(stream));
 }
 
 int bh_tree_export(const bh_tree* t, void* nodes, int32_t* perm, void* stream) {

@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
   nd.next = pre + 1;
   nd.first = first;
   nd.count = count;
-  nd.meta = 1 | (level << 8);
+  nd.meta = 1 | (count > 1 ? 2 : 0) | (level << 8);
   nodes[pre] = nd;
   Mx[3 * (int64_t)pre] = X;
   Mx[3 * (int64_t)pre + 1] = Y;

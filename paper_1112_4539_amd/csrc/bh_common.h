@@ -24,7 +24,8 @@ constexpr int kWave = 64;                   // CDNA wavefront width
 //   next  : preorder id of the first node after this subtree
 //   first : Morton position of the first particle of the subtree
 //   count : number of particles in the subtree
-//   meta  : bit 0 = leaf, bits 8..15 = level
+//   meta  : bit 0 = leaf, bit 1 = leaf holding several particles (coincident
+//           keys), bits 8..15 = level
 struct alignas(64) Node {
   double cx, cy, cz;
   double M;
@@ -36,6 +37,22 @@ struct alignas(64) Node {
   int32_t meta;
 };
 static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
+
+// The walk's copy of a node for one uniform theta: a cell carries its squared
+// opening size S = (l/theta + s)^2 in place of l, and the slot of s holds the
+// mass rounded to FP32.
+struct alignas(64) WalkNode {
+  double cx, cy, cz;
+  double M;
+  double S;
+  float M32;
+  int32_t pad;
+  int32_t next;
+  int32_t first;
+  int32_t count;
+  int32_t meta;
+};
+static_assert(sizeof(WalkNode) == 64, "WalkNode must be 64 bytes");
 
 // Root cube and Morton quantisation, computed on the device by the bbox pass.
 struct Cube {
@@ -56,7 +73,7 @@ struct Counts {
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 

@@ -34,6 +34,7 @@ struct BuildWs {
   uint32_t* lmask;          // [n + 1]
   Node* nodes;              // [2n]
   double* Mx;               // [2n][3]
+  WalkNode* wnodes;         // [2n] walk copy of the nodes for the last uniform theta
 };
 
 hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total, hipStream_t st);
@@ -51,6 +52,7 @@ struct WalkArgs {
   int n;
   double eps2;
   double inv_theta;            // 1/theta when theta_group is null
+  const WalkNode* wnodes;      // uniform theta: walk copy of the nodes (S and M32 precomputed)
   const float* theta_group;    // theta per 64-particle Morton group, may be null
   void* acc;                   // [n][3] caller order
   void* pot;                   // [n] caller order
@@ -58,6 +60,7 @@ struct WalkArgs {
   uint64_t* hash;              // stats: [n] ordered-list hash, caller order
   int64_t* lists;              // dump: [n][maxlen] list words, caller order
   int64_t maxlen;
+  int32_t* group_steps;        // stats: [ceil(n/64)] nodes visited per group, may be null
   int xcd_chunk;               // workgroups per XCD chunk of the block remap (0 = identity)
   int waves_per_block;         // 1, 2 or 4
 };
@@ -65,6 +68,12 @@ struct WalkArgs {
 enum WalkMode { kWalkForces = 0, kWalkStats = 1, kWalkDump = 2 };
 
 hipError_t launch_walk(bool f64, int mode, const WalkArgs& a, hipStream_t st);
+
+// Walk copy of the nodes for one uniform theta: every record with its side l
+// replaced by S = (l/theta + s)^2 (Eq. (2) squared, the S_effective of Sec. 4.4)
+// and its mass also in FP32.
+hipError_t launch_mac_size(const Node* nodes, const Counts* counts, int cap, double inv_theta,
+                           WalkNode* wnodes, hipStream_t st);
 
 // Direct sum of Eq. (1) for a list of targets (caller indices).
 hipError_t launch_direct(bool f64, const void* pos, const void* mass, int n, const int64_t* targets, int nt,
