@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--waves-per-block", type=int, default=4)
     ap.add_argument("--xcd-chunk", type=int, default=0)
     ap.add_argument("--target-order", type=int, default=0)
+    ap.add_argument("--lds-share", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -92,7 +93,7 @@ def main():
 
     def step():
         T = bh.Tree(gpos, gmass, workspace=ws)
-        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order)
+        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share)
         T.forces(args.theta, eps, acc=acc, pot=pot)
         return T
 
@@ -120,7 +121,7 @@ def main():
     ev0.record()
     for _ in range(args.steps):
         T = bh.Tree(gpos, gmass, workspace=ws)
-        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order)
+        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share)
         T.set_timing(True)
         T.forces(args.theta, eps, acc=acc, pot=pot)
         walk_ms.append(T)
@@ -178,7 +179,7 @@ def main():
             "rms_rel_force_err": rms, "accuracy_targets": None if rms is None else args.samples,
             "n_nodes": tstats["n_nodes"],
             "launch": {"waves_per_block": args.waves_per_block, "xcd_chunk": args.xcd_chunk,
-                       "target_order": args.target_order},
+                       "target_order": args.target_order, "lds_share": args.lds_share},
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -128,8 +128,11 @@ BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *st
 /* Launch shape of the walk: waves_per_block in {1, 2, 4}; xcd_chunk >= 0
  * (runs of workgroups kept on one XCD; 0 = plain order).  target_order 0 =
  * Morton order (groups of Morton-consecutive targets), 1 = caller order (the
- * paper's unsorted experiment, Sec. 5).  Results do not depend on any of them. */
-BH_API int bh_set_walk_config(bh_tree *t, int waves_per_block, int xcd_chunk, int target_order);
+ * paper's unsorted experiment, Sec. 5).  lds_share in [0, 64]: how many waves
+ * out of 64 read node records through LDS copies instead of the scalar cache.
+ * Results do not depend on any of them. */
+BH_API int bh_set_walk_config(bh_tree *t, int waves_per_block, int xcd_chunk, int target_order,
+                              int lds_share);
 
 /* Enable (1) or disable (0) HIP-event timing of the walk kernel; after a
  * timed walk, bh_walk_time_ms synchronises and returns its duration. */

@@ -49,7 +49,7 @@ def load():
         "bh_forces_theta": ([P, P, d, P, P, P], i32),
         "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P, P], i32),
         "bh_tree_export": ([P, P, P, P], i32),
-        "bh_set_walk_config": ([P, i32, i32, i32], i32),
+        "bh_set_walk_config": ([P, i32, i32, i32, i32], i32),
         "bh_set_timing": ([P, i32], i32),
         "bh_walk_time_ms": ([P, P], i32),
         "bh_tree_release": ([P], None),
@@ -134,11 +134,12 @@ class Tree:
         _check(lib.bh_build_tree(_ptr(self.pos), _ptr(self.mass), self.n, self.prec, _ptr(workspace),
                                  workspace.numel(), _stream(self.device), ctypes.byref(h)))
         self._h = h
+        self._release = lib.bh_tree_release  # kept for __del__ during interpreter shutdown
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            load().bh_tree_release(h)
+            self._release(h)
             self._h = None
 
     @property
@@ -155,8 +156,9 @@ class Tree:
                                     ctypes.byref(c)))
         return dict(n_nodes=a.value, n_leaves=b.value, n_internal=c.value)
 
-    def set_walk_config(self, waves_per_block=4, xcd_chunk=0, target_order=0):
-        _check(load().bh_set_walk_config(self._h, int(waves_per_block), int(xcd_chunk), int(target_order)))
+    def set_walk_config(self, waves_per_block=4, xcd_chunk=0, target_order=0, lds_share=16):
+        _check(load().bh_set_walk_config(self._h, int(waves_per_block), int(xcd_chunk), int(target_order),
+                                         int(lds_share)))
 
     def set_timing(self, enable=True):
         _check(load().bh_set_timing(self._h, 1 if enable else 0))

@@ -24,6 +24,7 @@ struct bh_tree {
   int waves_per_block = 4;
   int xcd_chunk = 0;
   int target_order = 0;
+  int lds_share64 = 16;
   bool timing = false;
   bool timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -158,6 +159,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.maxlen = maxlen;
   a.group_steps = group_steps;
   a.xcd_chunk = t->xcd_chunk;
+  a.lds_share64 = t->lds_share64;
   a.waves_per_block = t->waves_per_block;
   bh_tree* mt = const_cast<bh_tree*>(t);
   if (t->timing) {
@@ -280,12 +282,14 @@ int bh_tree_export(const bh_tree* t, void* nodes, int32_t* perm, void* stream) {
   return BH_OK;
 }
 
-int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int target_order) {
+int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int target_order, int lds_share) {
   if (!t) return fail(BH_EINVAL, "null tree");
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(BH_EINVAL, "waves_per_block must be 1, 2 or 4");
   if (xcd_chunk < 0) return fail(BH_EINVAL, "xcd_chunk must be >= 0");
   if (target_order != 0 && target_order != 1) return fail(BH_EINVAL, "target_order must be 0 or 1");
+  if (lds_share < 0 || lds_share > 64) return fail(BH_EINVAL, "lds_share must be in [0, 64]");
+  t->lds_share64 = lds_share;
   t->waves_per_block = waves_per_block;
   t->xcd_chunk = xcd_chunk;
   t->target_order = target_order;

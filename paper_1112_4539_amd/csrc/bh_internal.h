@@ -62,6 +62,7 @@ struct WalkArgs {
   int64_t maxlen;
   int32_t* group_steps;        // stats: [ceil(n/64)] nodes visited per group, may be null
   int xcd_chunk;               // workgroups per XCD chunk of the block remap (0 = identity)
+  int lds_share64;             // waves (out of 64) that read nodes through LDS copies
   int waves_per_block;         // 1, 2 or 4
 };
 

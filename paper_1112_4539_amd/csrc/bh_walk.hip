@@ -117,16 +117,6 @@ hipError_t launch_mac_size(const Node* nodes, const Counts* counts, int cap, dou
   return hipGetLastError();
 }
 
-// Per-lane state of one walk.
-template <bool kF64>
-struct Lane {
-  using R = typename std::conditional<kF64, double, float>::type;
-  typename std::conditional<kF64, AccF64, AccMixed>::type acc;
-  int32_t n_pp, n_pc;
-  uint64_t h;
-  int64_t len;
-};
-
 // What a step needs of a node, from the walk copy (uniform theta) or from the
 // plain node (per-group theta: S formed from l and s per lane).
 template <bool kPlain>
@@ -142,116 +132,188 @@ struct StepNode<true> {
   __device__ __forceinline__ Node load(int c) const { return base[c]; }
 };
 
-// The walk loop of one wavefront.  kGuard: some target of the wave has
-// theta > 1, so a cell holding the target must be excluded explicitly (for
-// theta <= 1 such a cell fails the opening test by itself: d <= (sqrt(3)/2) l
-// + s < l/theta + s, a margin of 0.13 l that no rounding reaches).
-// kPlain: read the plain nodes (per-group theta) rather than the walk copy.
+// One walk: a cursor over the preorder node array shared by the wave, and the
+// per-lane state of the lane's target.
+template <bool kF64>
+struct Cursor {
+  using R = typename std::conditional<kF64, double, float>::type;
+  typename std::conditional<kF64, AccF64, AccMixed>::type acc;
+  double xi, yi, zi;   // target position (exactly widened)
+  double inv_theta;
+  int i;               // Morton position of the target, -1 for an idle lane
+  int slot;            // position of the target in the walk order
+  int c;               // wave-uniform cursor
+  int skip;            // the lane is active at c iff skip <= c
+  int k, kend;         // position inside a leaf of several particles
+  int steps;
+  int32_t n_pp, n_pc;
+  uint64_t h;
+  int64_t len;
+  int64_t* list;
+};
+
+// One step of a walk at node `cur` (index cur_c = C.c).  kGuard: some target
+// of the wave has theta > 1, so a cell holding the target must be excluded
+// explicitly (for theta <= 1 such a cell fails the opening test by itself:
+// d <= (sqrt(3)/2) l + s < l/theta + s, a margin of 0.13 l that no rounding
+// reaches).
 //
-// Each step produces one source for the shared term: the cell (opening test
-// first), the particle of a one-particle leaf, or one particle of a leaf of
-// coincident-key particles (the cursor stays on such a leaf until its
-// particles are done).  One term site keeps the accumulators in place.
-template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard>
-__device__ __forceinline__ void walk_loop(const WalkArgs& a, StepNode<kPlain> wn, int i, int lane_valid,
-                                          double xi, double yi, double zi, float xf, float yf, float zf,
-                                          double inv_theta, Lane<kF64>& L, int64_t* mylist, int& steps) {
-  using R = typename Lane<kF64>::R;
+// Each step produces one source for the shared term: the cell (after the
+// opening test), the particle of a one-particle leaf, or one particle of a
+// leaf of coincident-key particles (the cursor stays on such a leaf until its
+// particles are done).  One term site keeps the sums in place.
+template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard, typename Rec>
+__device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64>& C, const Rec& rec) {
+  // The record was read from LDS by every lane; its integer fields steer the
+  // wave's control flow, so take them as wave-uniform values.
+  Rec cur = rec;
+  cur.next = uniform(rec.next);
+  cur.first = uniform(rec.first);
+  cur.count = uniform(rec.count);
+  cur.meta = uniform(rec.meta);
+  using R = typename Cursor<kF64>::R;
   using R4 = typename std::conditional<kF64, double4, float4>::type;
   constexpr bool kStats = kMode != kWalkForces;
   const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
-  const R eps2 = (R)a.eps2;
-  const int cap = 2 * a.n;
-  // next(root) is the node count; clamp it to the capacity so that a corrupted
-  // record can never send the cursor out of the array, and force progress.
-  const int n_nodes = min(uniform(wn.load(0).next), cap);
-  int skip = lane_valid ? 0 : 0x7fffffff;
-  int c = 0;
-  int k = 0, kend = 0;  // position inside a leaf of several particles
-  while (c < n_nodes) {
-    if constexpr (kStats) ++steps;
-    const auto cur = wn.load(c);
-    const int nnext = max(cur.next, c + 1);
-    const int kind = cur.meta & 3;  // 0 cell, 1 one-particle leaf, 3 several-particle leaf
-    const bool act = skip <= c;
-    const uint64_t m_act = ballot(act);
-    // Offset to the node's position (cell: centre of mass; one-particle leaf:
-    // its particle), formed in FP64.  For FP32 input the FP64 difference of the
-    // widened coordinates is exact, so its FP32 rounding equals a direct FP32
-    // subtraction; a cell's offset is rounded once.  Formed for every node so
-    // that the whole record is read at the top of the step.
-    double dx = cur.cx - xi, dy = cur.cy - yi, dz = cur.cz - zi;
-    // Opening test of Eq. (2) in FP64, also evaluated (and ignored) for leaves
-    // so that no field load is left for later in the step.
-    double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    double S;
-    if constexpr (kPlain) {
-      const double u = fma(cur.l, inv_theta, cur.s);
-      S = u * u;
-    } else {
-      S = cur.S;
+  const int c = C.c;
+  const int i = C.i;
+  if constexpr (kStats) ++C.steps;
+  const int nnext = max(cur.next, c + 1);
+  const int kind = cur.meta & 3;  // 0 cell, 1 one-particle leaf, 3 several-particle leaf
+  const bool act = C.skip <= c;
+  const uint64_t m_act = ballot(act);
+  // Offset to the node's position (cell: centre of mass; one-particle leaf:
+  // its particle), formed in FP64.  For FP32 input the FP64 difference of the
+  // widened coordinates is exact, so its FP32 rounding equals a direct FP32
+  // subtraction; a cell's offset is rounded once.  Formed for every node so
+  // that the whole record is read at the top of the step.
+  double dx = cur.cx - C.xi, dy = cur.cy - C.yi, dz = cur.cz - C.zi;
+  // Opening test of Eq. (2) in FP64, also evaluated (and ignored) for leaves
+  // so that no field load is left for later in the step.
+  double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  double S;
+  if constexpr (kPlain) {
+    const double u = fma(cur.l, C.inv_theta, cur.s);
+    S = u * u;
+  } else {
+    S = cur.S;
+  }
+  bool pass = d2 > S;
+  if constexpr (kGuard) pass = pass && !((unsigned)(i - cur.first) < (unsigned)cur.count);
+  // (a ballot is convergent: it keeps the test, and the loads it needs, here)
+  const uint64_t m_pass = ballot(pass);
+  R tm;
+  bool use;
+  uint64_t m_use;
+  int cnext = nnext;
+  int src = cur.first;  // Morton position of a particle source
+  if (kind == 0) {
+    // Cell: a cell term for the lanes that accept it.
+    use = act && pass;
+    m_use = m_act & m_pass;
+    if (m_act & ~m_pass) cnext = c + 1;
+    if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
+  } else if (kind == 1) {
+    // One-particle leaf: a particle term unless the particle is i.
+    use = act && cur.first != i;
+    m_use = m_act & ballot(cur.first != i);
+    if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
+  } else {
+    // Leaf of coincident-key particles: one of its particles per step.
+    if (C.kend == 0) {
+      C.k = min(max(cur.first, 0), a.n);
+      C.kend = C.k + min(max(cur.count, 0), a.n - C.k);
     }
-    bool pass = d2 > S;
-    if constexpr (kGuard) pass = pass && !((unsigned)(i - cur.first) < (unsigned)cur.count);
-    // (a ballot is convergent: it keeps the test, and the loads it needs, here)
-    const uint64_t m_pass = ballot(pass);
-    R tm;
-    bool use;
-    uint64_t m_use;
-    int cnext = nnext;
-    int src = cur.first;  // Morton position of a particle source
-    if (kind == 0) {
-      // Cell: a cell term for the lanes that accept it.
-      use = act && pass;
-      m_use = m_act & m_pass;
-      if (m_act & ~m_pass) cnext = c + 1;
-      if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
-    } else if (kind == 1) {
-      // One-particle leaf: a particle term unless the particle is i.
-      use = act && cur.first != i;
-      m_use = m_act & ballot(cur.first != i);
-      if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
+    const int kk = min(C.k, a.n - 1);
+    src = kk;
+    const R4 q = ps[kk];
+    use = act && C.k < C.kend && kk != i;
+    m_use = m_act & ballot(C.k < C.kend && kk != i);
+    // the step's source is this particle: its offset replaces the node's
+    dx = (double)q.x - C.xi;
+    dy = (double)q.y - C.yi;
+    dz = (double)q.z - C.zi;
+    d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    tm = q.w;
+    if (++C.k < C.kend) {
+      cnext = c;
     } else {
-      // Leaf of coincident-key particles: one of its particles per step.
-      if (kend == 0) {
-        k = min(max(cur.first, 0), a.n);
-        kend = k + min(max(cur.count, 0), a.n - k);
-      }
-      const int kk = min(k, a.n - 1);
-      src = kk;
-      const R4 q = ps[kk];
-      use = act && k < kend && kk != i;
-      m_use = m_act & ballot(k < kend && kk != i);
-      // the step's source is this particle: its offset replaces the node's
-      dx = (double)q.x - xi;
-      dy = (double)q.y - yi;
-      dz = (double)q.z - zi;
-      d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      tm = q.w;
-      if (++k < kend) {
-        cnext = c;
+      C.k = C.kend = 0;
+    }
+  }
+  if (m_use) {
+    if (use) {
+      if constexpr (kF64) {
+        C.acc.term(dx, dy, dz, tm, a.eps2);
       } else {
-        k = kend = 0;
+        C.acc.template term<kSoft>(dx, dy, dz, d2, tm, a.eps2);
+      }
+      if (kind == 0) C.skip = nnext;
+      if constexpr (kStats) {
+        const uint64_t wd = kind == 0 ? (((uint64_t)c << 1) | 1ull) : ((uint64_t)a.perm[src] << 1);
+        if (kind == 0) ++C.n_pc; else ++C.n_pp;
+        C.h = (C.h ^ wd) * kFnvPrime;
+        if (kMode == kWalkDump && C.len < a.maxlen) C.list[C.len] = (int64_t)wd;
+        ++C.len;
       }
     }
-    if (m_use) {
-      if (use) {
-        if constexpr (kF64) {
-          L.acc.term(dx, dy, dz, tm, eps2);
-        } else {
-          L.acc.template term<kSoft>(dx, dy, dz, d2, tm, a.eps2);
-        }
-        if (kind == 0) skip = nnext;
-        if constexpr (kStats) {
-          const uint64_t wd = kind == 0 ? (((uint64_t)c << 1) | 1ull) : ((uint64_t)a.perm[src] << 1);
-          if (kind == 0) ++L.n_pc; else ++L.n_pp;
-          L.h = (L.h ^ wd) * kFnvPrime;
-          if (kMode == kWalkDump && L.len < a.maxlen) mylist[L.len] = (int64_t)wd;
-          ++L.len;
-        }
-      }
+  }
+  C.c = cnext;
+}
+
+// Node records reach the walk through LDS.  The walk reads one record per
+// step and nearly every record misses the small scalar cache, whose miss
+// handling then sets the pace; the vector path has the throughput but a
+// longer latency.  So each step copies both possible successors of the
+// current node (c+1 and next(c)) with the LDS-DMA load (global_load_lds_dwordx4:
+// lanes 0-3 bring the four 16-byte quarters of one record, lanes 4-7 those
+// of the other) into the wave's spare buffer, and the next step reads the one
+// it needs with broadcast LDS reads.  The copy's latency overlaps one step.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename Rec>
+__device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int lane, uint4* dst) {
+  if (lane < 8) {
+    const int r = lane < 4 ? ca : cb;
+    const char* src = reinterpret_cast<const char*>(base + r) + (lane & 3) * 16;
+    __builtin_amdgcn_global_load_lds(src, (lds_void*)dst, 16, 0, 0);
+  }
+}
+
+// The plain form: each step reads its node with scalar loads (the record is
+// wave-uniform), one round trip per step.
+template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard>
+__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C) {
+  const int n_nodes = min(uniform(wn.load(0).next), 2 * a.n);
+  while (C.c < n_nodes) walk_step<kF64, kMode, kSoft, kPlain, kGuard>(a, C, wn.load(C.c));
+}
+
+template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard>
+__device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C,
+                                              uint4 (*pf)[8]) {
+  using Rec = decltype(wn.load(0));
+  // next(root) is the node count; clamp it to the capacity so that a corrupted
+  // record can never send the cursor out of the array.  Every step moves the
+  // cursor forward or stays on a leaf for at most its particle count.
+  const int cap = 2 * a.n;
+  const int n_nodes = min(uniform(wn.load(0).next), cap);
+  const int lane = __lane_id();
+  int buf = 0, slot = 0;  // LDS buffer and slot holding the current record
+  fetch_pair(wn.base, 0, 0, lane, pf[0]);
+  while (C.c < n_nodes) {
+    const int c = C.c;
+    // The copy issued last step is the only vector memory operation in flight
+    // here; the compiler does not order LDS-DMA writes before later LDS reads,
+    // so wait for it explicitly (s_waitcnt vmcnt(0)).
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    const Rec rec = reinterpret_cast<const Rec*>(pf[buf])[slot];
+    const int nnext = max(uniform(rec.next), c + 1);
+    fetch_pair(wn.base, min(c + 1, cap - 1), min(nnext, cap - 1), lane, pf[buf ^ 1]);
+    walk_step<kF64, kMode, kSoft, kPlain, kGuard>(a, C, rec);
+    if (C.c != c) {  // moved on (a leaf of several particles keeps the cursor)
+      slot = C.c == c + 1 ? 0 : 1;
+      buf ^= 1;
     }
-    c = cnext;
   }
 }
 
@@ -260,65 +322,72 @@ __device__ __forceinline__ void walk_loop(const WalkArgs& a, StepNode<kPlain> wn
 // (uniform theta walks the copy with S precomputed).
 template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
-  using R = typename Lane<kF64>::R;
+  using R = typename Cursor<kF64>::R;
   using R4 = typename std::conditional<kF64, double4, float4>::type;
   constexpr bool kStats = kMode != kWalkForces;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_chunk);
-  const int slot = (blk * a.waves_per_block + wv) * kWave + lane;
-  const bool valid = slot < a.n;
-  const int i = valid ? (a.order ? a.order[slot] : slot) : -1;  // Morton position of the target
   const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
 
+  Cursor<kF64> C;
+  C.slot = (blk * a.waves_per_block + wv) * kWave + lane;
+  const bool valid = C.slot < a.n;
+  C.i = valid ? (a.order ? a.order[C.slot] : C.slot) : -1;
   R4 me;
   if (valid) {
-    me = ps[i];
+    me = ps[C.i];
   } else {
     me.x = me.y = me.z = me.w = (R)0;
   }
-  const double xi = (double)me.x, yi = (double)me.y, zi = (double)me.z;
-  const double inv_theta = kGroupTheta ? 1.0 / (double)a.theta_group[valid ? (i >> 6) : 0] : a.inv_theta;
-  const bool guard = ballot(valid && inv_theta < 1.0) != 0ull;
+  C.xi = (double)me.x;
+  C.yi = (double)me.y;
+  C.zi = (double)me.z;
+  C.inv_theta = kGroupTheta ? 1.0 / (double)a.theta_group[valid ? (C.i >> 6) : 0] : a.inv_theta;
+  C.acc.init();
+  C.c = 0;
+  C.skip = valid ? 0 : 0x7fffffff;
+  C.k = C.kend = 0;
+  C.steps = 0;
+  C.n_pp = C.n_pc = 0;
+  C.h = kFnvOffset;
+  C.len = 0;
+  C.list = (kMode == kWalkDump && valid) ? a.lists + (int64_t)a.perm[C.i] * a.maxlen : nullptr;
+  const bool guard = ballot(valid && C.inv_theta < 1.0) != 0ull;
   StepNode<kGroupTheta> wn;
   if constexpr (kGroupTheta) wn.base = a.nodes; else wn.base = a.wnodes;
+  // per wave: two buffers of two 64-byte node records
+  __shared__ uint4 pf_lds[4][2][8];
+  // Waves split between the two node paths (scalar cache / LDS copies) so
+  // that neither the scalar cache nor instruction issue alone sets the pace;
+  // the share taking the LDS path is a launch parameter (results identical).
+  const int wave = blk * a.waves_per_block + wv;
+  const bool lds_path = ((wave * 37) & 63) < a.lds_share64;
+  if (lds_path) {
+    if (guard)
+      walk_loop_lds<kF64, kMode, kSoft, kGroupTheta, true>(a, wn, C, pf_lds[wv]);
+    else
+      walk_loop_lds<kF64, kMode, kSoft, kGroupTheta, false>(a, wn, C, pf_lds[wv]);
+  } else {
+    if (guard)
+      walk_loop_scalar<kF64, kMode, kSoft, kGroupTheta, true>(a, wn, C);
+    else
+      walk_loop_scalar<kF64, kMode, kSoft, kGroupTheta, false>(a, wn, C);
+  }
 
-  Lane<kF64> L;
-  L.acc.init();
-  L.n_pp = L.n_pc = 0;
-  L.h = kFnvOffset;
-  L.len = 0;
-  int64_t* mylist = nullptr;
-  if (kMode == kWalkDump && valid) mylist = a.lists + (int64_t)a.perm[i] * a.maxlen;
-  int steps = 0;
-  const float xf = (float)me.x, yf = (float)me.y, zf = (float)me.z;
-  if (guard)
-    walk_loop<kF64, kMode, kSoft, kGroupTheta, true>(a, wn, i, valid, xi, yi, zi, xf, yf, zf, inv_theta, L, mylist,
-                                                     steps);
-  else
-    walk_loop<kF64, kMode, kSoft, kGroupTheta, false>(a, wn, i, valid, xi, yi, zi, xf, yf, zf, inv_theta, L, mylist,
-                                                      steps);
-
-  if (kStats && a.group_steps && lane == 0 && valid) a.group_steps[slot >> 6] = steps;
+  if (kStats && a.group_steps && lane == 0 && valid) a.group_steps[C.slot >> 6] = C.steps;
   if (!valid) return;
-  const int o = a.perm[i];
+  const int o = a.perm[C.i];
   R* accp = reinterpret_cast<R*>(a.acc);
   R* potp = reinterpret_cast<R*>(a.pot);
-  if constexpr (kF64) {
-    accp[3 * (int64_t)o] = L.acc.ax;
-    accp[3 * (int64_t)o + 1] = L.acc.ay;
-    accp[3 * (int64_t)o + 2] = L.acc.az;
-    potp[o] = L.acc.p;
-  } else {
-    accp[3 * (int64_t)o] = (float)L.acc.ax;
-    accp[3 * (int64_t)o + 1] = (float)L.acc.ay;
-    accp[3 * (int64_t)o + 2] = (float)L.acc.az;
-    potp[o] = (float)L.acc.p;
-  }
+  accp[3 * (int64_t)o] = (R)C.acc.ax;
+  accp[3 * (int64_t)o + 1] = (R)C.acc.ay;
+  accp[3 * (int64_t)o + 2] = (R)C.acc.az;
+  potp[o] = (R)C.acc.p;
   if constexpr (kStats) {
-    a.counts[2 * (int64_t)o] = L.n_pp;
-    a.counts[2 * (int64_t)o + 1] = L.n_pc;
-    a.hash[o] = L.h;
+    a.counts[2 * (int64_t)o] = C.n_pp;
+    a.counts[2 * (int64_t)o + 1] = C.n_pc;
+    a.hash[o] = C.h;
   }
 }
 
@@ -326,8 +395,7 @@ template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
 static hipError_t launch_t(const WalkArgs& a, hipStream_t st) {
   const int groups = (a.n + kWave - 1) / kWave;
   const int wpb = a.waves_per_block;
-  const int blocks = (groups + wpb - 1) / wpb;
-  k_walk<kF64, kMode, kSoft, kGroupTheta><<<blocks, wpb * kWave, 0, st>>>(a);
+  k_walk<kF64, kMode, kSoft, kGroupTheta><<<(groups + wpb - 1) / wpb, wpb * kWave, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ def test_host_side_argument_checks():
     assert b"workspace" in lib.bh_last_error()
     assert lib.bh_forces(None, 0.5, 0.01, None, None, None) == -1
     assert lib.bh_direct(None, None, 10, 0, None, 5, -1.0, None, None, None) == -1
-    assert lib.bh_set_walk_config(None, 4, 0, 0) == -1
+    assert lib.bh_set_walk_config(None, 4, 0, 0, 0) == -1
 
 
 def test_theta_bound_matches_header():

@@ -197,9 +197,10 @@ def test_launch_shapes_and_target_order_bitexact(bh):
     for wpb in (1, 2, 4):
         for chunk in (0, 4, 16):
             for order in (0, 1):
-                T.set_walk_config(wpb, chunk, order)
-                a, p = T.forces(0.5, 1e-4)
-                assert torch.equal(a, ref[0]) and torch.equal(p, ref[1]), (wpb, chunk, order)
+                for share in (0, 24, 64):
+                    T.set_walk_config(wpb, chunk, order, share)
+                    a, p = T.forces(0.5, 1e-4)
+                    assert torch.equal(a, ref[0]) and torch.equal(p, ref[1]), (wpb, chunk, order, share)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
