@@ -31,6 +31,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload, theta):
+    """HBM bytes per walk launch from the committed counter summary, or None.
+
+    The figure holds only for the kernel source it was counted on: the summary
+    stores a digest of the walk's sources and is ignored once they changed.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"walk_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    if h.hexdigest() != rec["source_sha256"] or abs(rec.get("theta", theta) - theta) > 1e-12:
+        return None
+    return rec["traffic_bytes"]
+
+
 def cpu_baseline(pos32, mass32, theta, eps, seed, n_sample):
     """The FP64 CPU oracle on this host: full tree build + walk of a target sample, scaled."""
     import oracle
@@ -69,6 +88,8 @@ def main():
     ap.add_argument("--xcd-chunk", type=int, default=0)
     ap.add_argument("--target-order", type=int, default=0)
     ap.add_argument("--lds-share", type=int, default=16)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="first run three plain device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -77,6 +98,16 @@ def main():
 
     import paper_1112_4539_amd as bh
     from paper_1112_4539_amd import inputs
+
+    if args.copy_calib > 0:
+        # a plain copy of known size: reads and writes exactly MIB MiB each
+        src = torch.ones(args.copy_calib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] copy calibration: 3 x {args.copy_calib} MiB")
 
     pos, mass, spec = inputs.make(args.workload)
     eps = spec["eps"]
@@ -183,7 +214,8 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": measured_traffic(args.workload, args.theta),
             "kernel": "bh::k_walk<false,0>", "flops_per_unit": FLOPS_PER_INTERACTION,
             "units_per_launch": inter,
         },
