@@ -73,6 +73,77 @@ def cpu_baseline(pos32, mass32, theta, eps, seed, n_sample):
                 build_s=t1 - t0, walk_sample_s=t2 - t1)
 
 
+def forest_bench(args, bh, inputs):
+    """512 independent Plummer clusters (log-uniform N in [1024, 65536], seed 3), theta 0.5,
+    eps 0.01, FP32: the whole pipeline (forest build + walk) as one captured HIP graph with the
+    autotuned walk shape, against a build and a walk per cluster."""
+    pos, mass, off = inputs.clusters(512, 3)
+    n = len(pos)
+    theta, eps = 0.5, 0.01
+    dev = torch.device("cuda:0")
+    gpos = torch.tensor(pos.astype(np.float32), device=dev)
+    gmass = torch.tensor(mass.astype(np.float32), device=dev)
+    goff = torch.tensor(off, device=dev)
+    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((n,), dtype=torch.float32, device=dev)
+    log(f"[bench] forest: {len(off) - 1} clusters, n={n}")
+    F = bh.build_forest(gpos, gmass, goff)
+    F.check()
+    st = F.walk_stats(theta, eps)
+    inter = int(st["counts"].to(torch.int64).sum().item())
+    del st
+    best, tried = F.autotune(theta, eps, acc, pot, reps=2)
+    log(f"[bench] autotuned walk shape {best} ({len(tried)} candidates)")
+    G = F.graph(theta, eps, acc, pot)
+    for _ in range(args.warmup):
+        G.launch()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        G.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / args.steps
+    # walk alone, autotuned shape (HIP events around the walk kernel)
+    F.set_timing(True)
+    wt = []
+    for _ in range(args.steps):
+        F.forces(theta, eps, acc, pot)
+        wt.append(F.walk_time_ms())
+    walk_ms = float(np.mean(wt))
+    # one build and one walk per cluster, default shape
+    sub = [(int(off[k]), int(off[k + 1])) for k in range(len(off) - 1)]
+    ws = torch.empty(bh.workspace_bytes(int(np.max(np.diff(off))), bh.FP32), dtype=torch.uint8, device=dev)
+
+    def per_cluster():
+        for b, e in sub:
+            T = bh.Tree(gpos[b:e], gmass[b:e], workspace=ws)
+            T.forces(theta, eps, acc[b:e], pot[b:e])
+
+    per_cluster()
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 3))
+    ev0.record()
+    for _ in range(reps):
+        per_cluster()
+    ev1.record()
+    torch.cuda.synchronize()
+    per_ms = ev0.elapsed_time(ev1) / reps
+    line = {
+        "metric": "particle-interactions/s, 512 clusters in one captured launch",
+        "value": inter / (graph_ms * 1e-3), "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": graph_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"512 Plummer clusters, N log-uniform in [1024, 65536], seed 3, n={n}, "
+                               f"theta={theta}, eps={eps}, FP32",
+                   "interactions_per_step": inter, "graph_ms": graph_ms, "walk_ms": walk_ms,
+                   "per_cluster_ms": per_ms, "speedup_vs_per_cluster": per_ms / graph_ms,
+                   "autotuned": best, "candidates": tried},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +159,7 @@ def main():
     ap.add_argument("--xcd-chunk", type=int, default=0)
     ap.add_argument("--target-order", type=int, default=0)
     ap.add_argument("--lds-share", type=int, default=16)
+    ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -98,6 +170,9 @@ def main():
 
     import paper_1112_4539_amd as bh
     from paper_1112_4539_amd import inputs
+
+    if args.workload == "clusters512":
+        return forest_bench(args, bh, inputs)
 
     if args.copy_calib > 0:
         # a plain copy of known size: reads and writes exactly MIB MiB each
@@ -124,7 +199,8 @@ def main():
 
     def step():
         T = bh.Tree(gpos, gmass, workspace=ws)
-        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share)
+        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share,
+                          args.persistent)
         T.forces(args.theta, eps, acc=acc, pot=pot)
         return T
 
@@ -152,7 +228,8 @@ def main():
     ev0.record()
     for _ in range(args.steps):
         T = bh.Tree(gpos, gmass, workspace=ws)
-        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share)
+        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share,
+                          args.persistent)
         T.set_timing(True)
         T.forces(args.theta, eps, acc=acc, pot=pot)
         walk_ms.append(T)
@@ -210,7 +287,8 @@ def main():
             "rms_rel_force_err": rms, "accuracy_targets": None if rms is None else args.samples,
             "n_nodes": tstats["n_nodes"],
             "launch": {"waves_per_block": args.waves_per_block, "xcd_chunk": args.xcd_chunk,
-                       "target_order": args.target_order, "lds_share": args.lds_share},
+                       "target_order": args.target_order, "lds_share": args.lds_share,
+                       "persistent": args.persistent},
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

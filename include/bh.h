@@ -45,6 +45,16 @@ extern "C" {
 #endif
 
 typedef struct bh_tree bh_tree;
+typedef struct bh_graph bh_graph;
+
+/* Launch shape of the walk (see bh_set_walk_config); ms = measured walk time. */
+typedef struct bh_walk_config {
+  int waves_per_block;
+  int xcd_chunk;
+  int lds_share;
+  int persistent;
+  float ms;
+} bh_walk_config;
 
 #define BH_FP32 0
 #define BH_FP64 1
@@ -94,8 +104,9 @@ BH_API int bh_tree_stats(const bh_tree *t, void *stream, int64_t *n_nodes, int64
  *   theta: in (0, 2/sqrt(3)) -- beyond it a cell could be accepted by a
  *          particle inside it.  eps >= 0 and finite.
  *   acc [n][3], pot [n]: device outputs, caller order, tree precision.
- * BH_FP32 trees evaluate terms in FP32 with FP64 opening tests and cell
- * offsets and compensated FP32 sums; BH_FP64 trees evaluate in FP64. */
+ * BH_FP32 trees evaluate terms in FP32 (r^2 + eps^2 rounded once, hardware
+ * inverse square root) with FP64 opening tests, FP64 offsets and FP64 sums;
+ * BH_FP64 trees evaluate every term in FP64. */
 BH_API int bh_forces(const bh_tree *t, double theta, double eps, void *acc, void *pot, void *stream);
 
 /* Same walk with one opening parameter per Morton group of 64 particles:
@@ -109,7 +120,9 @@ BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double ep
  * terms) and hash [n] = ordered-list hash: h = (h xor w) * 1099511628211 from
  * h = 14695981039346656037 over the list words w, w = j<<1 for a particle term
  * with source j (caller index), w = c<<1|1 for a cell term with node c
- * (depth-first preorder id).  If lists != NULL it also writes the first maxlen
+ * (depth-first preorder id).  In a forest both are relative to the target's
+ * cluster (j - offsets[k], c - root of cluster k), so a cluster's words equal
+ * those of the same cluster built alone.  If lists != NULL it also writes the first maxlen
  * words of each list to lists [n][maxlen] (entries past the list are left as
  * they were).  If group_steps != NULL it receives, per group of 64 targets of
  * the walk (ceil(n/64) int32), the number of nodes the group's wavefront
@@ -130,9 +143,12 @@ BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *st
  * Morton order (groups of Morton-consecutive targets), 1 = caller order (the
  * paper's unsorted experiment, Sec. 5).  lds_share in [0, 64]: how many waves
  * out of 64 read node records through LDS copies instead of the scalar cache.
+ * persistent 0 = one wavefront per group of 64 targets, 1 = a grid that fits
+ * the chip at once whose wavefronts take groups from a device counter (kept in
+ * the workspace: two walks of one tree must not run concurrently).
  * Results do not depend on any of them. */
 BH_API int bh_set_walk_config(bh_tree *t, int waves_per_block, int xcd_chunk, int target_order,
-                              int lds_share);
+                              int lds_share, int persistent);
 
 /* Enable (1) or disable (0) HIP-event timing of the walk kernel; after a
  * timed walk, bh_walk_time_ms synchronises and returns its duration. */
@@ -141,6 +157,53 @@ BH_API int bh_walk_time_ms(const bh_tree *t, float *ms);
 
 /* Release a tree handle (host object only; the workspace stays the caller's). */
 BH_API void bh_tree_release(bh_tree *t);
+
+/* ---- Batched forest: many independent clusters in one build and one walk.
+ * (Sec. 4.4 applied cluster by cluster; the batching itself is beyond the paper.) */
+
+/* Workspace of a forest of n particles in n_clusters clusters (1 <= n_clusters
+ * <= 2^24); -1 for invalid arguments.  bh_workspace_bytes(n, p) equals
+ * bh_forest_workspace_bytes(n, 1, p). */
+BH_API int64_t bh_forest_workspace_bytes(int64_t n, int64_t n_clusters, int prec);
+
+/* Build one tree per cluster: cluster k is the caller's particles [offsets[k],
+ * offsets[k+1]) (offsets: device int64 [n_clusters+1], 0 = offsets[0] <= ... <=
+ * offsets[n_clusters] = n; may be NULL for one cluster).  Each cluster gets
+ * its own root cube, Morton order and tree, exactly as bh_build_tree would
+ * build it alone; the clusters' particles stay in their ranges and their
+ * subtrees are consecutive preorder ranges (bh_forest_roots).  bh_forces,
+ * bh_forces_theta, bh_walk_stats and bh_tree_export then work on the forest: a
+ * particle feels only its own cluster, and its result is bit-identical to the
+ * single-cluster build.  Bad offsets are reported by bh_tree_check (BH_EINVAL);
+ * the build never reads or writes outside its arrays because of them.  The
+ * offsets array must stay valid while the tree is used. */
+BH_API int bh_build_forest(const void *pos, const void *mass, const int64_t *offsets, int64_t n_clusters,
+                           int64_t n, int prec, void *workspace, int64_t ws_bytes, void *stream, bh_tree **out);
+
+/* Copy the preorder id of every cluster's root to roots [n_clusters+1] (device
+ * int32; roots[n_clusters] = node count).  Synchronises the stream. */
+BH_API int bh_forest_roots(const bh_tree *t, int32_t *roots, void *stream);
+
+/* Capture the whole force pipeline of tree t -- the build from the arrays t was
+ * built from (same pointers, re-read at every launch) and bh_forces with theta
+ * and eps into acc/pot -- as one HIP graph, with the walk shape set on t at
+ * capture time.  The capture runs on a stream of the library's own (after
+ * synchronising `stream`) and executes nothing.  bh_graph_launch enqueues one
+ * replay on `stream`; t then describes the replayed build.  Replays and other
+ * calls on t must not overlap.  The graph holds no memory of its own. */
+BH_API int bh_graph_create(bh_tree *t, double theta, double eps, void *acc, void *pot, void *stream,
+                           bh_graph **out);
+BH_API int bh_graph_launch(bh_graph *g, void *stream);
+BH_API void bh_graph_release(bh_graph *g);
+
+/* Pick the walk shape of t by measurement: runs bh_forces (theta, eps, acc, pot)
+ * reps times per candidate, one knob at a time (persistent, waves_per_block,
+ * lds_share, xcd_chunk), keeps the fastest (HIP-event walk time, best of reps),
+ * sets it on t and returns it in *best.  If tried != NULL the first max_tried
+ * candidates measured are written there and *n_tried gets their number.
+ * Synchronises the stream; results of the walk do not depend on the choice. */
+BH_API int bh_autotune(bh_tree *t, double theta, double eps, void *acc, void *pot, int reps, void *stream,
+                       bh_walk_config *best, bh_walk_config *tried, int max_tried, int *n_tried);
 
 /* Brute-force sum of Eq. (1) over all j != i for nt targets (Sec. 3):
  * pos [n][3], mass [n] device in precision prec; targets [nt] device int64

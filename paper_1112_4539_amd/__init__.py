@@ -14,8 +14,8 @@ import os
 
 import torch
 
-__all__ = ["Tree", "build_tree", "direct", "workspace_bytes", "load", "THETA_MAX",
-           "BHError", "FP32", "FP64"]
+__all__ = ["Tree", "Forest", "Graph", "build_tree", "build_forest", "direct", "workspace_bytes",
+           "forest_workspace_bytes", "load", "THETA_MAX", "BHError", "FP32", "FP64", "WalkConfig"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbh.so")
@@ -27,6 +27,15 @@ _lib = None
 
 class BHError(RuntimeError):
     pass
+
+
+class WalkConfig(ctypes.Structure):
+    """``bh_walk_config``: a launch shape of the walk and its measured time."""
+    _fields_ = [("waves_per_block", ctypes.c_int), ("xcd_chunk", ctypes.c_int), ("lds_share", ctypes.c_int),
+                ("persistent", ctypes.c_int), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def load():
@@ -42,14 +51,21 @@ def load():
         "bh_last_error": ([], ctypes.c_char_p),
         "bh_version": ([], i32),
         "bh_workspace_bytes": ([i64, i32], i64),
+        "bh_forest_workspace_bytes": ([i64, i64, i32], i64),
         "bh_build_tree": ([P, P, i64, i32, P, i64, P, P], i32),
+        "bh_build_forest": ([P, P, P, i64, i64, i32, P, i64, P, P], i32),
+        "bh_forest_roots": ([P, P, P], i32),
+        "bh_graph_create": ([P, d, d, P, P, P, P], i32),
+        "bh_graph_launch": ([P, P], i32),
+        "bh_graph_release": ([P], None),
+        "bh_autotune": ([P, d, d, P, P, i32, P, P, P, i32, P], i32),
         "bh_tree_check": ([P, P], i32),
         "bh_tree_stats": ([P, P, P, P, P], i32),
         "bh_forces": ([P, d, d, P, P, P], i32),
         "bh_forces_theta": ([P, P, d, P, P, P], i32),
         "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P, P], i32),
         "bh_tree_export": ([P, P, P, P], i32),
-        "bh_set_walk_config": ([P, i32, i32, i32, i32], i32),
+        "bh_set_walk_config": ([P, i32, i32, i32, i32, i32], i32),
         "bh_set_timing": ([P, i32], i32),
         "bh_walk_time_ms": ([P, P], i32),
         "bh_tree_release": ([P], None),
@@ -94,6 +110,13 @@ def workspace_bytes(n, prec):
     return int(v)
 
 
+def forest_workspace_bytes(n, n_clusters, prec):
+    v = load().bh_forest_workspace_bytes(int(n), int(n_clusters), int(prec))
+    if v < 0:
+        raise ValueError(f"invalid n={n}, n_clusters={n_clusters} or precision={prec}")
+    return int(v)
+
+
 NODE_DTYPE = None
 
 
@@ -113,7 +136,7 @@ class Tree:
     keeps references to them and to its workspace tensor.
     """
 
-    def __init__(self, pos, mass, workspace=None):
+    def __init__(self, pos, mass, workspace=None, offsets=None):
         lib = load()
         if pos.device.type != "cuda" or mass.device.type != "cuda":
             raise ValueError("pos and mass must be device tensors")
@@ -126,13 +149,22 @@ class Tree:
             raise ValueError("pos must be [n,3] and mass [n]")
         self.n = int(self.pos.shape[0])
         self.device = self.pos.device
-        need = workspace_bytes(self.n, self.prec)
+        self.offsets = None
+        self.n_clusters = 1
+        if offsets is not None:
+            if offsets.dtype != torch.int64 or offsets.device != self.device or offsets.dim() != 1 \
+                    or offsets.shape[0] < 2:
+                raise ValueError("offsets must be an int64 device tensor [n_clusters+1]")
+            self.offsets = offsets.contiguous()
+            self.n_clusters = int(offsets.shape[0]) - 1
+        need = forest_workspace_bytes(self.n, self.n_clusters, self.prec)
         if workspace is None or workspace.numel() < need:
             workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
         self.workspace = workspace
         h = ctypes.c_void_p()
-        _check(lib.bh_build_tree(_ptr(self.pos), _ptr(self.mass), self.n, self.prec, _ptr(workspace),
-                                 workspace.numel(), _stream(self.device), ctypes.byref(h)))
+        _check(lib.bh_build_forest(_ptr(self.pos), _ptr(self.mass), _ptr(self.offsets), self.n_clusters, self.n,
+                                   self.prec, _ptr(workspace), workspace.numel(), _stream(self.device),
+                                   ctypes.byref(h)))
         self._h = h
         self._release = lib.bh_tree_release  # kept for __del__ during interpreter shutdown
 
@@ -156,9 +188,30 @@ class Tree:
                                     ctypes.byref(c)))
         return dict(n_nodes=a.value, n_leaves=b.value, n_internal=c.value)
 
-    def set_walk_config(self, waves_per_block=4, xcd_chunk=0, target_order=0, lds_share=16):
+    def set_walk_config(self, waves_per_block=4, xcd_chunk=0, target_order=0, lds_share=16, persistent=0):
         _check(load().bh_set_walk_config(self._h, int(waves_per_block), int(xcd_chunk), int(target_order),
-                                         int(lds_share)))
+                                         int(lds_share), int(persistent)))
+
+    def autotune(self, theta, eps, acc=None, pot=None, reps=2, max_tried=64):
+        """Pick the walk shape by measurement (``bh_autotune``); returns (best, tried) as dicts."""
+        acc, pot = self._outs(acc, pot)
+        best = WalkConfig()
+        tried = (WalkConfig * max_tried)()
+        nt = ctypes.c_int()
+        _check(load().bh_autotune(self._h, float(theta), float(eps), _ptr(acc), _ptr(pot), int(reps),
+                                  _stream(self.device), ctypes.byref(best), tried, int(max_tried),
+                                  ctypes.byref(nt)))
+        return best.as_dict(), [tried[i].as_dict() for i in range(min(nt.value, max_tried))]
+
+    def roots(self):
+        """Preorder id of every cluster's root, plus the node count (``bh_forest_roots``)."""
+        r = torch.empty((self.n_clusters + 1,), dtype=torch.int32, device=self.device)
+        _check(load().bh_forest_roots(self._h, _ptr(r), _stream(self.device)))
+        return r
+
+    def graph(self, theta, eps, acc, pot):
+        """Capture build + forces into acc/pot as one HIP graph (``bh_graph_create``)."""
+        return Graph(self, theta, eps, acc, pot)
 
     def set_timing(self, enable=True):
         _check(load().bh_set_timing(self._h, 1 if enable else 0))
@@ -229,8 +282,40 @@ class Tree:
         return rec, perm.cpu().numpy()[: self.n].astype(np.int64)
 
 
+class Graph:
+    """The captured pipeline of a tree: every launch rebuilds from the tree's input tensors
+    (their current contents) and writes the forces to the captured acc/pot."""
+
+    def __init__(self, tree, theta, eps, acc, pot):
+        acc, pot = tree._outs(acc, pot)
+        self.tree, self.acc, self.pot = tree, acc, pot
+        g = ctypes.c_void_p()
+        _check(load().bh_graph_create(tree._h, float(theta), float(eps), _ptr(acc), _ptr(pot),
+                                      _stream(tree.device), ctypes.byref(g)))
+        self._g = g
+        self._release = load().bh_graph_release
+
+    def launch(self):
+        _check(load().bh_graph_launch(self._g, _stream(self.tree.device)))
+        return self.acc, self.pot
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g is not None and g.value:
+            self._release(g)
+            self._g = None
+
+
+Forest = Tree
+
+
 def build_tree(pos, mass, workspace=None):
     return Tree(pos, mass, workspace)
+
+
+def build_forest(pos, mass, offsets, workspace=None):
+    """One tree per cluster [offsets[k], offsets[k+1]) in one build (``bh_build_forest``)."""
+    return Tree(pos, mass, workspace, offsets=offsets)
 
 
 def direct(pos, mass, eps, targets=None):

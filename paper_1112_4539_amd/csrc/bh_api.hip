@@ -18,16 +18,26 @@ hipError_t make_rank(const int32_t* perm, int n, int32_t* rank, hipStream_t st);
 
 struct bh_tree {
   int64_t n = 0;
+  int64_t n_seg = 1;
   int prec = BH_FP32;
+  const void* pos = nullptr;       // build inputs, kept for graph replays
+  const void* mass = nullptr;
   bh::BuildWs w{};
   int32_t* rank = nullptr;  // caller index -> Morton position
+  int32_t* queue = nullptr; // group counter of the persistent walk
   int waves_per_block = 4;
   int xcd_chunk = 0;
   int target_order = 0;
   int lds_share64 = 16;
+  int persistent = 0;
   bool timing = false;
   bool timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct bh_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -47,13 +57,14 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 constexpr int64_t kMaxN = int64_t(1) << 30;
+constexpr int64_t kMaxClusters = int64_t(1) << 24;
 constexpr size_t kAlign = 256;
 const double kThetaMax = 2.0 / std::sqrt(3.0);
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Carves the workspace; with base == nullptr it only measures.
-size_t layout(int64_t n, int prec, char* base, bh::BuildWs* w, int32_t** rank) {
+size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_t** rank, int32_t** queue) {
   const size_t N = (size_t)(n > 0 ? n : 1);
   const size_t nodes = 2 * N;
   const size_t sort_tiles = (N + bh::kSortTile - 1) / bh::kSortTile;
@@ -68,8 +79,16 @@ size_t layout(int64_t n, int prec, char* base, bh::BuildWs* w, int32_t** rank) {
     return p;
   };
   bh::BuildWs t{};
-  t.cube = reinterpret_cast<bh::Cube*>(take(sizeof(bh::Cube)));
+  t.n_seg = (int)K;
+  t.cube = reinterpret_cast<bh::Cube*>(take(sizeof(bh::Cube) * (size_t)K));
   t.counts = reinterpret_cast<bh::Counts*>(take(sizeof(bh::Counts)));
+  t.own_off = reinterpret_cast<int64_t*>(take(2 * sizeof(int64_t)));
+  t.seg_off = t.own_off;
+  t.croot = reinterpret_cast<int32_t*>(take(4 * ((size_t)K + 1)));
+  int32_t* q = reinterpret_cast<int32_t*>(take(4));
+  t.seg = reinterpret_cast<int32_t*>(take(4 * N));
+  t.scid = reinterpret_cast<int32_t*>(take(4 * N));
+  t.ucid = reinterpret_cast<int32_t*>(take(4 * N));
   t.bbox_part = reinterpret_cast<double*>(take(sizeof(double) * 6 * bh::kBboxBlocks));
   t.n_bbox_blocks = bh::kBboxBlocks;
   t.key_a = reinterpret_cast<uint64_t*>(take(8 * N));
@@ -99,6 +118,7 @@ size_t layout(int64_t n, int prec, char* base, bh::BuildWs* w, int32_t** rank) {
   int32_t* r = reinterpret_cast<int32_t*>(take(4 * N));
   if (w) *w = t;
   if (rank) *rank = r;
+  if (queue) *queue = q;
   return off;
 }
 
@@ -119,9 +139,20 @@ int sync_counts(const bh_tree* t, hipStream_t st, bh::Counts* c) {
   return BH_OK;
 }
 
+hipError_t enqueue_build(const bh_tree* t, hipStream_t st) {
+  const int n = (int)t->n;
+  hipError_t e = t->prec == BH_FP64
+                     ? bh::build_tree_f64(static_cast<const double*>(t->pos), static_cast<const double*>(t->mass), n,
+                                          t->w, st)
+                     : bh::build_tree_f32(static_cast<const float*>(t->pos), static_cast<const float*>(t->mass), n,
+                                          t->w, st);
+  if (e == hipSuccess && n > 0) e = bh::make_rank(t->w.idx_a, n, t->rank, st);
+  return e;
+}
+
 int run_walk(const bh_tree* t, double theta, const float* theta_group, double eps, void* acc, void* pot,
              int mode, int32_t* counts, uint64_t* hash, int64_t* lists, int64_t maxlen, int32_t* group_steps,
-             hipStream_t st) {
+             hipStream_t st, bool allow_timing = true) {
   if (!t) return fail(BH_EINVAL, "null tree");
   if (!theta_group) {
     int rc = check_theta_eps(theta, eps);
@@ -147,6 +178,10 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.ps = t->w.ps;
   a.perm = t->w.idx_a;
   a.order = t->target_order == 1 ? t->rank : nullptr;
+  a.scid = t->w.scid;
+  a.croot = t->w.croot;
+  a.seg_off = t->w.seg_off;
+  a.n_seg = (int)t->n_seg;
   a.n = (int)t->n;
   a.eps2 = eps * eps;
   a.inv_theta = theta_group ? 0.0 : 1.0 / theta;
@@ -161,14 +196,21 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.xcd_chunk = t->xcd_chunk;
   a.lds_share64 = t->lds_share64;
   a.waves_per_block = t->waves_per_block;
+  a.persistent = t->persistent;
+  a.queue = t->queue;
+  if (t->persistent) {
+    a.grid = bh::persistent_grid(t->prec == BH_FP64, mode, eps * eps > 0.0, theta_group != nullptr, t->waves_per_block);
+    if (a.grid <= 0) return fail(BH_EHIP, "cannot size the persistent walk grid");
+  }
   bh_tree* mt = const_cast<bh_tree*>(t);
-  if (t->timing) {
+  const bool timing = t->timing && allow_timing;
+  if (timing) {
     hipError_t e = hipEventRecord(t->ev0, st);
     if (e != hipSuccess) return hip_fail(e, "recording the walk start event");
   }
   hipError_t e = bh::launch_walk(t->prec == BH_FP64, mode, a, st);
   if (e != hipSuccess) return hip_fail(e, "launching the tree walk");
-  if (t->timing) {
+  if (timing) {
     e = hipEventRecord(t->ev1, st);
     if (e != hipSuccess) return hip_fail(e, "recording the walk end event");
     mt->timed = true;
@@ -184,42 +226,52 @@ const char* bh_last_error(void) { return g_err; }
 
 int bh_version(void) { return 1; }
 
-int64_t bh_workspace_bytes(int64_t n, int prec) {
-  if (n < 0 || n > kMaxN || (prec != BH_FP32 && prec != BH_FP64)) return -1;
-  return (int64_t)layout(n, prec, nullptr, nullptr, nullptr);
+int64_t bh_forest_workspace_bytes(int64_t n, int64_t n_clusters, int prec) {
+  if (n < 0 || n > kMaxN || n_clusters < 1 || n_clusters > kMaxClusters || (prec != BH_FP32 && prec != BH_FP64))
+    return -1;
+  return (int64_t)layout(n, n_clusters, prec, nullptr, nullptr, nullptr, nullptr);
 }
 
-int bh_build_tree(const void* pos, const void* mass, int64_t n, int prec, void* workspace, int64_t ws_bytes,
-                  void* stream, bh_tree** out) {
+int64_t bh_workspace_bytes(int64_t n, int prec) { return bh_forest_workspace_bytes(n, 1, prec); }
+
+int bh_build_forest(const void* pos, const void* mass, const int64_t* offsets, int64_t n_clusters, int64_t n,
+                    int prec, void* workspace, int64_t ws_bytes, void* stream, bh_tree** out) {
   if (!out) return fail(BH_EINVAL, "out must not be null");
   *out = nullptr;
   if (n < 0 || n > kMaxN) return fail(BH_EINVAL, "n must be in [0, 2^30]; got %lld", (long long)n);
+  if (n_clusters < 1 || n_clusters > kMaxClusters)
+    return fail(BH_EINVAL, "n_clusters must be in [1, 2^24]; got %lld", (long long)n_clusters);
   if (prec != BH_FP32 && prec != BH_FP64) return fail(BH_EINVAL, "prec must be BH_FP32 or BH_FP64");
   const size_t el = prec == BH_FP64 ? 8 : 4;
   if (n > 0 && (!pos || !mass || !aligned(pos, el) || !aligned(mass, el)))
     return fail(BH_EINVAL, "pos/mass must be non-null device arrays aligned to %zu bytes", el);
-  const int64_t need = bh_workspace_bytes(n, prec);
+  if (offsets && !aligned(offsets, 8)) return fail(BH_EINVAL, "offsets must be 8-byte aligned");
+  if (!offsets && n_clusters != 1) return fail(BH_EINVAL, "offsets are required for more than one cluster");
+  const int64_t need = bh_forest_workspace_bytes(n, n_clusters, prec);
   if (!workspace || ws_bytes < need)
     return fail(BH_ENOSPC, "workspace of %lld bytes needed, %lld given", (long long)need, (long long)ws_bytes);
   if (!aligned(workspace, kAlign)) return fail(BH_EINVAL, "workspace must be 256-byte aligned");
   bh_tree* t = new (std::nothrow) bh_tree();
   if (!t) return fail(BH_EINVAL, "out of host memory");
   t->n = n;
+  t->n_seg = n_clusters;
   t->prec = prec;
-  layout(n, prec, static_cast<char*>(workspace), &t->w, &t->rank);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = prec == BH_FP64
-                     ? bh::build_tree_f64(static_cast<const double*>(pos), static_cast<const double*>(mass), (int)n,
-                                          t->w, st)
-                     : bh::build_tree_f32(static_cast<const float*>(pos), static_cast<const float*>(mass), (int)n,
-                                          t->w, st);
-  if (e == hipSuccess && n > 0) e = bh::make_rank(t->w.idx_a, (int)n, t->rank, st);
+  t->pos = pos;
+  t->mass = mass;
+  layout(n, n_clusters, prec, static_cast<char*>(workspace), &t->w, &t->rank, &t->queue);
+  if (offsets) t->w.seg_off = offsets;
+  hipError_t e = enqueue_build(t, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     delete t;
     return hip_fail(e, "launching the tree build");
   }
   *out = t;
   return BH_OK;
+}
+
+int bh_build_tree(const void* pos, const void* mass, int64_t n, int prec, void* workspace, int64_t ws_bytes,
+                  void* stream, bh_tree** out) {
+  return bh_build_forest(pos, mass, nullptr, 1, n, prec, workspace, ws_bytes, stream, out);
 }
 
 int bh_tree_check(const bh_tree* t, void* stream) {
@@ -282,14 +334,17 @@ int bh_tree_export(const bh_tree* t, void* nodes, int32_t* perm, void* stream) {
   return BH_OK;
 }
 
-int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int target_order, int lds_share) {
+int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int target_order, int lds_share,
+                       int persistent) {
   if (!t) return fail(BH_EINVAL, "null tree");
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(BH_EINVAL, "waves_per_block must be 1, 2 or 4");
   if (xcd_chunk < 0) return fail(BH_EINVAL, "xcd_chunk must be >= 0");
   if (target_order != 0 && target_order != 1) return fail(BH_EINVAL, "target_order must be 0 or 1");
   if (lds_share < 0 || lds_share > 64) return fail(BH_EINVAL, "lds_share must be in [0, 64]");
+  if (persistent != 0 && persistent != 1) return fail(BH_EINVAL, "persistent must be 0 or 1");
   t->lds_share64 = lds_share;
+  t->persistent = persistent;
   t->waves_per_block = waves_per_block;
   t->xcd_chunk = xcd_chunk;
   t->target_order = target_order;
@@ -337,6 +392,142 @@ int bh_direct(const void* pos, const void* mass, int64_t n, int prec, const int6
   hipError_t e = bh::launch_direct(prec == BH_FP64, pos, mass, (int)n, targets, (int)nt, eps, acc, pot,
                                    static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "launching the direct sum");
+  return BH_OK;
+}
+
+int bh_forest_roots(const bh_tree* t, int32_t* roots, void* stream) {
+  if (!t || !roots || !aligned(roots, 4)) return fail(BH_EINVAL, "null tree or misaligned roots array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(roots, t->w.croot, 4 * (size_t)(t->n_seg + 1), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "copying cluster roots");
+  return BH_OK;
+}
+
+int bh_graph_create(bh_tree* t, double theta, double eps, void* acc, void* pot, void* stream, bh_graph** out) {
+  if (!out) return fail(BH_EINVAL, "out must not be null");
+  *out = nullptr;
+  if (!t) return fail(BH_EINVAL, "null tree");
+  int rc = check_theta_eps(theta, eps);
+  if (rc) return rc;
+  const size_t el = t->prec == BH_FP64 ? 8 : 4;
+  if (t->n > 0 && (!acc || !pot || !aligned(acc, el) || !aligned(pot, el)))
+    return fail(BH_EINVAL, "acc/pot must be non-null device arrays aligned to %zu bytes", el);
+  // Capture needs a stream of its own (the caller's may be the null stream);
+  // the first use on it waits for the caller's pending work.
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "creating the capture stream");
+  e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  bh_graph* g = nullptr;
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    hipError_t eb = enqueue_build(t, cs);
+    int wrc = eb == hipSuccess ? run_walk(t, theta, nullptr, eps, acc, pot, bh::kWalkForces, nullptr, nullptr,
+                                          nullptr, 0, nullptr, cs, false)
+                               : BH_OK;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (eb != hipSuccess) e = eb;
+    if (e == hipSuccess && wrc != BH_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cs);
+      return wrc;
+    }
+    if (e == hipSuccess) {
+      g = new (std::nothrow) bh_graph();
+      if (!g) {
+        (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        return fail(BH_EINVAL, "out of host memory");
+      }
+      g->graph = graph;
+      e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        g = nullptr;
+      }
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return hip_fail(e, "capturing the force pipeline");
+  *out = g;
+  return BH_OK;
+}
+
+int bh_graph_launch(bh_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(BH_EINVAL, "null graph");
+  hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the captured pipeline");
+  return BH_OK;
+}
+
+void bh_graph_release(bh_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+int bh_autotune(bh_tree* t, double theta, double eps, void* acc, void* pot, int reps, void* stream,
+                bh_walk_config* best, bh_walk_config* tried, int max_tried, int* n_tried) {
+  if (!t || !best) return fail(BH_EINVAL, "null tree or result");
+  if (reps < 1 || reps > 100) return fail(BH_EINVAL, "reps must be in [1, 100]");
+  if (tried && max_tried < 0) return fail(BH_EINVAL, "max_tried must be >= 0");
+  int rc = check_theta_eps(theta, eps);
+  if (rc) return rc;
+  if (n_tried) *n_tried = 0;
+  const bool was_timing = t->timing;
+  if ((rc = bh_set_timing(t, 1)) != BH_OK) return rc;
+  bh_walk_config cur{t->waves_per_block, t->xcd_chunk, t->lds_share64, t->persistent, 0.f};
+  auto measure = [&](bh_walk_config& c) -> int {
+    t->waves_per_block = c.waves_per_block;
+    t->xcd_chunk = c.xcd_chunk;
+    t->lds_share64 = c.lds_share;
+    t->persistent = c.persistent;
+    float bestms = 0.f;
+    for (int r = 0; r < reps; ++r) {
+      int q = bh_forces(t, theta, eps, acc, pot, stream);
+      if (q != BH_OK) return q;
+      float ms = 0.f;
+      if ((q = bh_walk_time_ms(t, &ms)) != BH_OK) return q;
+      if (r == 0 || ms < bestms) bestms = ms;
+    }
+    c.ms = bestms;
+    if (tried && n_tried && *n_tried < max_tried) tried[*n_tried] = c;
+    if (n_tried) ++*n_tried;
+    return BH_OK;
+  };
+  // coordinate search: one knob at a time, keeping the best so far
+  if ((rc = measure(cur)) != BH_OK) return rc;
+  static const int kPersistent[] = {0, 1};
+  static const int kWpb[] = {1, 2, 4};
+  static const int kShare[] = {0, 8, 16, 32};
+  static const int kChunk[] = {0, 2, 8};
+  for (int stage = 0; stage < 4 && rc == BH_OK; ++stage) {
+    const int* vals = stage == 0 ? kPersistent : stage == 1 ? kWpb : stage == 2 ? kShare : kChunk;
+    const int nv = stage == 0 ? 2 : stage == 1 ? 3 : stage == 2 ? 4 : 3;
+    if (stage == 3 && cur.persistent) break;  // the block remap does not apply to the persistent walk
+    bh_walk_config stage_best = cur;
+    for (int v = 0; v < nv; ++v) {
+      bh_walk_config c = cur;
+      int* knob = stage == 0 ? &c.persistent : stage == 1 ? &c.waves_per_block : stage == 2 ? &c.lds_share
+                                                                                            : &c.xcd_chunk;
+      if (*knob == vals[v]) continue;
+      *knob = vals[v];
+      if ((rc = measure(c)) != BH_OK) break;
+      if (c.ms < stage_best.ms) stage_best = c;
+    }
+    cur = stage_best;
+  }
+  t->waves_per_block = cur.waves_per_block;
+  t->xcd_chunk = cur.xcd_chunk;
+  t->lds_share64 = cur.lds_share;
+  t->persistent = cur.persistent;
+  (void)bh_set_timing(t, was_timing ? 1 : 0);
+  if (rc != BH_OK) return rc;
+  *best = cur;
   return BH_OK;
 }
 

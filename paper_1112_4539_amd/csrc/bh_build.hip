@@ -175,18 +175,9 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const T* __restrict__ pos,
   }
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nb, int64_t n, Cube* __restrict__ cube) {
-  if (threadIdx.x != 0) return;
-  double lo[3], hi[3];
-  for (int d = 0; d < 3; ++d) {
-    lo[d] = INFINITY;
-    hi[d] = -INFINITY;
-  }
-  for (int b = 0; b < nb; ++b)
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = fmin(lo[d], part[b * 6 + d]);
-      hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
-    }
+// Root cube from the coordinate-wise extremes: lo = minimum corner, side L =
+// largest extent (1 if every particle coincides or there is none).
+__device__ void finish_cube(double lo[3], double hi[3], Cube* __restrict__ cube) {
   double L = 0.0;
   for (int d = 0; d < 3; ++d) {
     if (!(lo[d] <= hi[d])) {  // no finite particle at all
@@ -200,6 +191,93 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nb, int64_t n,
   for (int d = 0; d < 3; ++d) cube->lo[d] = lo[d];
   cube->L = L;
   cube->scale = (double)kGrid / L;
+}
+
+// One wave folds the per-block extremes (min and max are exact, so the order
+// does not matter).
+__global__ __launch_bounds__(64) void k_bbox_final(const double* __restrict__ part, int nb, Cube* __restrict__ cube) {
+  const int lane = threadIdx.x;
+  double v[6];
+  for (int k = 0; k < 6; ++k) v[k] = k < 3 ? INFINITY : -INFINITY;
+  for (int b = lane; b < nb; b += 64)
+    for (int k = 0; k < 6; ++k) v[k] = k < 3 ? fmin(v[k], part[b * 6 + k]) : fmax(v[k], part[b * 6 + k]);
+  for (int k = 0; k < 6; ++k)
+    for (int o = 32; o > 0; o >>= 1) {
+      double u = __shfl_xor(v[k], o, 64);
+      v[k] = k < 3 ? fmin(v[k], u) : fmax(v[k], u);
+    }
+  if (lane == 0) finish_cube(v, v + 3, cube);
+}
+
+// Offsets of a forest: off[0] = 0, nondecreasing, off[K] = n.  A violation is
+// reported through bad_input; every later pass clamps ranges to [0, n], so a bad
+// offset array can give wrong trees but never an access out of bounds.
+__global__ __launch_bounds__(256) void k_seg_check(const int64_t* __restrict__ off, int K, int64_t n,
+                                                   Counts* __restrict__ cnt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > K) return;
+  const int64_t v = off[k];
+  bool bad = v < 0 || v > n || (k == 0 && v != 0) || (k == K && v != n) || (k < K && off[k + 1] < v);
+  if (bad) atomicOr(&cnt->bad_input, 2);
+}
+
+__global__ void k_single_off(int64_t* __restrict__ off, int64_t n) {
+  if (threadIdx.x == 0) {
+    off[0] = 0;
+    off[1] = n;
+  }
+}
+
+__device__ __forceinline__ int64_t clamp_off(int64_t v, int64_t n) { return v < 0 ? 0 : (v > n ? n : v); }
+
+// Cluster of caller index i: the k with off[k] <= i < off[k+1].
+__device__ __forceinline__ int seg_of(const int64_t* __restrict__ off, int K, int64_t i) {
+  int lo = 0, hi = K;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Root cube of every cluster of a forest: one workgroup per cluster.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bbox_seg(const T* __restrict__ pos, const T* __restrict__ mass,
+                                                  const int64_t* __restrict__ off, int64_t n,
+                                                  Cube* __restrict__ cube, Counts* __restrict__ cnt) {
+  __shared__ double red[6][4];
+  const int k = blockIdx.x;
+  const int64_t b = clamp_off(off[k], n), e = max(b, clamp_off(off[k + 1], n));
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+    for (int d = 0; d < 3; ++d) {
+      double x = (double)pos[3 * i + d];
+      if (!isfinite(x)) {
+        bad = true;
+      } else {
+        v[d] = fmin(v[d], x);
+        v[3 + d] = fmax(v[3 + d], x);
+      }
+    }
+    if (!isfinite((double)mass[i])) bad = true;
+  }
+  if (__any(bad) && lane_id() == 0) atomicOr(&cnt->bad_input, 1);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int q = 0; q < 6; ++q) {
+    for (int o = 32; o > 0; o >>= 1) {
+      double u = __shfl_xor(v[q], o, 64);
+      v[q] = q < 3 ? fmin(v[q], u) : fmax(v[q], u);
+    }
+    if (lane == 0) red[q][w] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 6; ++q)
+      for (int r = 1; r < 4; ++r) red[q][0] = q < 3 ? fmin(red[q][0], red[q][r]) : fmax(red[q][0], red[q][r]);
+    double lo[3] = {red[0][0], red[1][0], red[2][0]}, hi[3] = {red[3][0], red[4][0], red[5][0]};
+    finish_cube(lo, hi, cube + k);
+  }
 }
 
 // ---------------------------------------------------------------- Morton keys
@@ -227,10 +305,14 @@ __device__ __forceinline__ uint32_t compact3(uint64_t v) {
 // bits with x as the most significant bit of each triplet, so the octant of a
 // child is 4*bx + 2*by + bz and key order is depth-first (Morton) order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, int n, const Cube* __restrict__ cube,
+__global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, int n, const Cube* __restrict__ cubes,
+                                              const int64_t* __restrict__ off, int K, int32_t* __restrict__ seg,
                                               uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int k = K > 1 ? seg_of(off, K, i) : 0;
+  seg[i] = k;
+  const Cube* cube = cubes + k;
   const double sc = cube->scale;
   uint64_t q[3];
 #pragma unroll
@@ -245,7 +327,18 @@ __global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, int n, 
 }
 
 // ---------------------------------------------------------------- radix sort
-__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __restrict__ keys, int n, int shift,
+// Digit of item i of a pass: 8 bits of its key, or (kSeg) 8 bits of its
+// cluster, looked up through its caller index.
+template <bool kSeg>
+__device__ __forceinline__ uint32_t digit_of(uint64_t key, int32_t val, const int32_t* __restrict__ seg, int shift) {
+  if constexpr (kSeg) return ((uint32_t)seg[val] >> shift) & 255u;
+  return (uint32_t)(key >> shift) & 255u;
+}
+
+template <bool kSeg>
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __restrict__ keys,
+                                                          const int32_t* __restrict__ vals,
+                                                          const int32_t* __restrict__ seg, int n, int shift,
                                                           int32_t* __restrict__ hist, int ntiles) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -254,7 +347,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __rest
 #pragma unroll 4
   for (int r = 0; r < kSortItems; ++r) {
     int64_t i = base + r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    if (i < n) atomicAdd(&h[digit_of<kSeg>(kSeg ? 0ull : keys[i], kSeg ? vals[i] : 0, seg, shift)], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = (int32_t)h[threadIdx.x];
@@ -262,8 +355,10 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __rest
 
 // Stable scatter: items of a tile are ranked in input order; within a wave the
 // rank among equal digits comes from 8 ballots (one per digit bit).
+template <bool kSeg>
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                              const int32_t* __restrict__ vin,
+                                                             const int32_t* __restrict__ seg,
                                                              uint64_t* __restrict__ kout,
                                                              int32_t* __restrict__ vout, int n, int shift,
                                                              const int32_t* __restrict__ offs, int ntiles) {
@@ -281,7 +376,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __r
     bool valid = i < n;
     uint64_t key = valid ? kin[i] : 0ull;
     int32_t val = valid ? vin[i] : 0;
-    uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint32_t d = valid ? digit_of<kSeg>(key, val, seg, shift) : 0u;
     uint64_t peers = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -310,13 +405,23 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __r
   }
 }
 
+__global__ __launch_bounds__(256) void k_copy_kv(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                 uint64_t* __restrict__ kout, int32_t* __restrict__ vout, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  kout[i] = kin[i];
+  vout[i] = vin[i];
+}
+
 // ---------------------------------------------------------------- gather
 template <typename T, typename T4>
 __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ pos, const T* __restrict__ mass,
-                                                const int32_t* __restrict__ perm, int n, T4* __restrict__ ps) {
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ seg,
+                                                int n, T4* __restrict__ ps, int32_t* __restrict__ scid) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int64_t j = perm[k];
+  scid[k] = seg[j];
   T4 v;
   v.x = pos[3 * j];
   v.y = pos[3 * j + 1];
@@ -326,29 +431,54 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ pos, const
 }
 
 // ---------------------------------------------------------------- unique keys
-__global__ __launch_bounds__(256) void k_unique_flags(const uint64_t* __restrict__ keys, int n,
+// A leaf per distinct (cluster, key).
+__global__ __launch_bounds__(256) void k_unique_flags(const uint64_t* __restrict__ keys,
+                                                      const int32_t* __restrict__ scid, int n,
                                                       int32_t* __restrict__ flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+  flag[i] = (i == 0 || keys[i] != keys[i - 1] || scid[i] != scid[i - 1]) ? 1 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_unique_write(const uint64_t* __restrict__ keys, int n,
+__global__ __launch_bounds__(256) void k_unique_write(const uint64_t* __restrict__ keys,
+                                                      const int32_t* __restrict__ scid, int n,
                                                       const int32_t* __restrict__ flag,
                                                       const int32_t* __restrict__ uid,
                                                       uint64_t* __restrict__ ukey, int32_t* __restrict__ ustart,
-                                                      Counts* __restrict__ cnt) {
+                                                      int32_t* __restrict__ ucid, Counts* __restrict__ cnt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (flag[i]) {
     ukey[uid[i]] = keys[i];
     ustart[uid[i]] = i;
+    ucid[uid[i]] = scid[i];
   }
   if (i == n - 1) {
     int U = uid[i] + flag[i];
     ustart[U] = n;
     cnt->n_unique = U;
   }
+}
+
+// First unique key of every cluster (the sort keeps cluster k at Morton
+// positions [off[k], off[k+1])); U for an empty trailing cluster.
+__global__ __launch_bounds__(256) void k_croot_first(const int64_t* __restrict__ off, int K, int n,
+                                                     const int32_t* __restrict__ uid,
+                                                     const Counts* __restrict__ cnt, int32_t* __restrict__ croot) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > K) return;
+  const int64_t b = clamp_off(off[k], n);
+  croot[k] = b < n ? uid[b] : cnt->n_unique;
+}
+
+// Preorder id of the cluster's root: the shallowest node starting at its first
+// unique key u, u + #internal nodes starting before u; for k = K the node count.
+__global__ __launch_bounds__(256) void k_croot_final(int K, const int32_t* __restrict__ nexcl,
+                                                     int32_t* __restrict__ croot) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > K) return;
+  const int u = croot[k];
+  croot[k] = u + nexcl[u];
 }
 
 // ---------------------------------------------------------------- topology
@@ -369,7 +499,11 @@ __device__ __forceinline__ bool same_cell(uint64_t a, uint64_t b, int level) {
 // boundaries.  Its key range [f, l] is found by galloping + binary search
 // (keys are sorted, so a range shares a prefix iff its ends do).  The pair is
 // the cell's representative iff it is the first child boundary in the range.
-__global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey, const Counts* __restrict__ cnt,
+//
+// Keys of different clusters share no cell: such a pair gets split level -1 and
+// bounds every search.
+__global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey, const int32_t* __restrict__ ucid,
+                                               const Counts* __restrict__ cnt,
                                                int32_t* __restrict__ split, int32_t* __restrict__ rep,
                                                int32_t* __restrict__ pf, int32_t* __restrict__ pl, int nmax) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -379,14 +513,21 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
     rep[j] = 0;
     return;
   }
+  const int cj = ucid[j];
+  if (ucid[j + 1] != cj) {
+    split[j] = -1;
+    rep[j] = 0;
+    return;
+  }
   const uint64_t kj = ukey[j], kj1 = ukey[j + 1];
   const int s = split_level(kj, kj1);
   split[j] = s;
+  auto in_cell = [&](int m, uint64_t ref) { return ucid[m] == cj && same_cell(ukey[m], ref, s); };
   // first key of the cell: smallest f <= j with same_cell(ukey[f], kj, s)
   int lo = j, step = 1;
   while (true) {
     int cand = j - step;
-    if (cand < 0 || !same_cell(ukey[cand], kj, s)) break;
+    if (cand < 0 || !in_cell(cand, kj)) break;
     lo = cand;
     step <<= 1;
   }
@@ -395,7 +536,7 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
   if (a < -1) a = -1;
   while (b - a > 1) {
     int m = a + (b - a) / 2;
-    if (same_cell(ukey[m], kj, s)) b = m; else a = m;
+    if (in_cell(m, kj)) b = m; else a = m;
   }
   const int f = b;
   // last key of the cell: largest l >= j+1 with same_cell(ukey[l], kj1, s)
@@ -403,7 +544,7 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
   step = 1;
   while (true) {
     int cand = j + 1 + step;
-    if (cand >= U || !same_cell(ukey[cand], kj1, s)) break;
+    if (cand >= U || !in_cell(cand, kj1)) break;
     up = cand;
     step <<= 1;
   }
@@ -411,7 +552,7 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
   if (d > U) d = U;
   while (d - c > 1) {
     int m = c + (d - c) / 2;
-    if (same_cell(ukey[m], kj1, s)) c = m; else d = m;
+    if (in_cell(m, kj1)) c = m; else d = m;
   }
   const int l = c;
   bool is_rep = (f == j) || (s < kLevels - 1 && same_cell(ukey[f], kj, s + 1));
@@ -452,7 +593,8 @@ __global__ __launch_bounds__(256) void k_internal_write(const int32_t* __restric
 //   pre(leaf x)     = x + #internal nodes starting at or before x
 //   next(v)         = pre(leaf last(v)) + 1
 template <typename T4>
-__global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict__ cnt, const Cube* __restrict__ cube,
+__global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict__ cnt, const Cube* __restrict__ cubes,
+                                                        const int32_t* __restrict__ ucid,
                                                         const int32_t* __restrict__ ilevel,
                                                         const int32_t* __restrict__ ifirst,
                                                         const int32_t* __restrict__ ilast,
@@ -467,6 +609,7 @@ __global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict
   const int s = ilevel[v], f = ifirst[v], l = ilast[v];
   const int pre = f + nexcl[f] + __popc(lmask[f] & ((1u << s) - 1u));
   ipre[v] = pre;
+  const Cube* cube = cubes + ucid[f];
   Node nd;
   nd.cx = nd.cy = nd.cz = 0.0;
   nd.M = 0.0;
@@ -480,7 +623,8 @@ __global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict
 }
 
 template <typename T4>
-__global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ cnt, const Cube* __restrict__ cube,
+__global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ cnt, const Cube* __restrict__ cubes,
+                                                    const int32_t* __restrict__ ucid,
                                                     const int32_t* __restrict__ split,
                                                     const int32_t* __restrict__ nstart,
                                                     const int32_t* __restrict__ nexcl,
@@ -491,11 +635,12 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
   if (x >= nmax || x >= U) return;
   const int pre = x + nexcl[x] + nstart[x];
   const int first = ustart[x], count = ustart[x + 1] - first;
+  const Cube* cube = cubes + ucid[x];
+  // a leaf sits one level below the deeper of its two neighbour splits (split
+  // -1 marks a cluster edge, so a cluster's only key is its level-0 root)
   int level;
   if (count > 1) {
     level = kLevels;
-  } else if (U == 1) {
-    level = 0;
   } else {
     int sl = (x > 0) ? split[x - 1] : -1;
     int sr = (x < U - 1) ? split[x] : -1;
@@ -551,7 +696,8 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
 
 // Moments of the internal nodes of one level (children are deeper, so they are
 // final).  Children are pre+1, next(pre+1), ... < next(pre), in octant order.
-__global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict__ cnt, const Cube* __restrict__ cube,
+__global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict__ cnt, const Cube* __restrict__ cubes,
+                                                       const int32_t* __restrict__ ucid,
                                                        const int32_t* __restrict__ ilevel,
                                                        const int32_t* __restrict__ ifirst,
                                                        const int32_t* __restrict__ ipre,
@@ -560,6 +706,7 @@ __global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict_
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nmax || v >= cnt->n_internal || ilevel[v] != level) return;
   const int p = ipre[v];
+  const Cube* cube = cubes + ucid[ifirst[v]];
   const int n_nodes = cnt->n_nodes;
   const int end = min(nodes[p].next, n_nodes);
   double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
@@ -603,46 +750,73 @@ static inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t) > 0 ? (
 template <typename T, typename T4>
 static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& w, hipStream_t st) {
   hipError_t e;
+  const int K = w.n_seg;
   k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(w.counts), sizeof(Counts) / 4, 0);
+  if (w.seg_off == w.own_off) k_single_off<<<1, 64, 0, st>>>(w.own_off, n);
+  k_seg_check<<<nblk(K + 1, 256), 256, 0, st>>>(w.seg_off, K, n, w.counts);
+  // cluster roots for an empty build: every cluster starts and ends at node 0
+  k_fill_i32<<<nblk(K + 1, 256), 256, 0, st>>>(w.croot, K + 1, 0);
   if (n == 0) return hipGetLastError();
-  // root cube
-  const int nbb = w.n_bbox_blocks;
-  k_bbox_partial<T><<<nbb, 256, 0, st>>>(pos, mass, n, w.bbox_part, w.counts);
-  k_bbox_final<<<1, 64, 0, st>>>(w.bbox_part, nbb, n, w.cube);
-  // keys and stable sort
-  k_keys<T><<<nblk(n, 256), 256, 0, st>>>(pos, n, w.cube, w.key_a, w.idx_a);
+  // root cubes
+  if (K == 1) {
+    const int nbb = w.n_bbox_blocks;
+    k_bbox_partial<T><<<nbb, 256, 0, st>>>(pos, mass, n, w.bbox_part, w.counts);
+    k_bbox_final<<<1, 64, 0, st>>>(w.bbox_part, nbb, w.cube);
+  } else {
+    k_bbox_seg<T><<<K, 256, 0, st>>>(pos, mass, w.seg_off, n, w.cube, w.counts);
+  }
+  // keys and stable sort by (cluster, key): 8 key passes, then the cluster digits
+  k_keys<T><<<nblk(n, 256), 256, 0, st>>>(pos, n, w.cube, w.seg_off, K, w.seg, w.key_a, w.idx_a);
   const int ntiles = (n + kSortTile - 1) / kSortTile;
+  int seg_passes = 0;
+  for (unsigned r = (unsigned)(K - 1); r; r >>= 8) ++seg_passes;
   uint64_t *kin = w.key_a, *kout = w.key_b;
   int32_t *vin = w.idx_a, *vout = w.idx_b;
-  for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 8 * pass;
-    k_rs_hist<<<ntiles, kSortThreads, 0, st>>>(kin, n, shift, w.hist, ntiles);
+  for (int pass = 0; pass < 8 + seg_passes; ++pass) {
+    const bool segp = pass >= 8;
+    const int shift = segp ? 8 * (pass - 8) : 8 * pass;
+    if (segp)
+      k_rs_hist<true><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, n, shift, w.hist, ntiles);
+    else
+      k_rs_hist<false><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, n, shift, w.hist, ntiles);
     if ((e = scan_excl(w.hist, w.hist, 256 * ntiles, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
-    k_rs_scatter<<<ntiles, kSortThreads, 0, st>>>(kin, vin, kout, vout, n, shift, w.hist, ntiles);
+    if (segp)
+      k_rs_scatter<true><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, kout, vout, n, shift, w.hist, ntiles);
+    else
+      k_rs_scatter<false><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, kout, vout, n, shift, w.hist, ntiles);
     uint64_t* tk = kin; kin = kout; kout = tk;
     int32_t* tv = vin; vin = vout; vout = tv;
   }
-  // after an even number of passes the sorted data is back in key_a / idx_a
-  k_gather<T, T4><<<nblk(n, 256), 256, 0, st>>>(pos, mass, w.idx_a, n, reinterpret_cast<T4*>(w.ps));
-  // unique keys
-  k_unique_flags<<<nblk(n, 256), 256, 0, st>>>(w.key_a, n, w.flag);
+  // the sorted data must end in key_a / idx_a
+  if (kin != w.key_a) k_copy_kv<<<nblk(n, 256), 256, 0, st>>>(kin, vin, w.key_a, w.idx_a, n);
+  k_gather<T, T4><<<nblk(n, 256), 256, 0, st>>>(pos, mass, w.idx_a, w.seg, n, reinterpret_cast<T4*>(w.ps), w.scid);
+  // unique (cluster, key) pairs
+  k_unique_flags<<<nblk(n, 256), 256, 0, st>>>(w.key_a, w.scid, n, w.flag);
   if ((e = scan_excl(w.flag, w.uid, n, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
-  k_unique_write<<<nblk(n, 256), 256, 0, st>>>(w.key_a, n, w.flag, w.uid, w.ukey, w.ustart, w.counts);
+  k_unique_write<<<nblk(n, 256), 256, 0, st>>>(w.key_a, w.scid, n, w.flag, w.uid, w.ukey, w.ustart, w.ucid,
+                                               w.counts);
+  k_croot_first<<<nblk(K + 1, 256), 256, 0, st>>>(w.seg_off, K, n, w.uid, w.counts, w.croot);
   // internal nodes
-  k_pairs<<<nblk(n, 256), 256, 0, st>>>(w.ukey, w.counts, w.split, w.flag, w.pf, w.pl, n);
+  k_pairs<<<nblk(n, 256), 256, 0, st>>>(w.ukey, w.ucid, w.counts, w.split, w.flag, w.pf, w.pl, n);
   if ((e = scan_excl(w.flag, w.uid, n, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
   k_fill_i32<<<nblk(n + 1, 256), 256, 0, st>>>(w.nstart, n + 1, 0);
   k_fill_i32<<<nblk(n + 1, 256), 256, 0, st>>>(reinterpret_cast<int32_t*>(w.lmask), n + 1, 0);
   k_internal_write<<<nblk(n, 256), 256, 0, st>>>(w.flag, w.uid, w.split, w.pf, w.pl, w.counts, w.ilevel, w.ifirst,
                                                  w.ilast, w.nstart, w.lmask, n);
   if ((e = scan_excl(w.nstart, w.nexcl, n + 1, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
-  k_nodes_internal<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ilevel, w.ifirst, w.ilast, w.nstart,
-                                                     w.nexcl, w.lmask, w.ustart, w.ipre, w.nodes, n);
-  k_nodes_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.split, w.nstart, w.nexcl, w.ustart,
+  k_croot_final<<<nblk(K + 1, 256), 256, 0, st>>>(K, w.nexcl, w.croot);
+  k_nodes_internal<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ucid, w.ilevel, w.ifirst, w.ilast,
+                                                     w.nstart, w.nexcl, w.lmask, w.ustart, w.ipre, w.nodes, n);
+  k_nodes_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ucid, w.split, w.nstart, w.nexcl, w.ustart,
                                                  reinterpret_cast<const T4*>(w.ps), w.nodes, w.Mx, n);
   for (int level = kLevels - 1; level >= 0; --level)
-    k_moments_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ilevel, w.ifirst, w.ipre, w.ukey, w.nodes,
-                                                  w.Mx, level, n);
+    k_moments_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ucid, w.ilevel, w.ifirst, w.ipre, w.ukey,
+                                                  w.nodes, w.Mx, level, n);
+  return hipGetLastError();
+}
+
+hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  k_fill_i32<<<nblk(n, 256), 256, 0, st>>>(p, n, v);
   return hipGetLastError();
 }
 

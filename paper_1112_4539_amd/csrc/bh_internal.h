@@ -14,10 +14,22 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kBboxBlocks = 1024;
 
-// Views into the caller's workspace used by one tree build.
+// Views into the caller's workspace used by one build.  A build covers K >= 1
+// independent clusters (a forest): cluster k is the caller's particles
+// [off[k], off[k+1]) and gets its own root cube, keys and tree.  The sort puts
+// the clusters one after the other in Morton order, so every cluster keeps its
+// particle range, and its subtree is the preorder node range [croot[k],
+// croot[k+1]).  A single tree is the forest with K = 1.
 struct BuildWs {
-  Cube* cube;
+  Cube* cube;               // [K] root cube per cluster
   Counts* counts;
+  int n_seg;                // K
+  const int64_t* seg_off;   // [K+1] cluster offsets (device; the caller's or own_off)
+  int64_t* own_off;         // [2] offsets {0, n} of a single tree
+  int32_t* seg;             // [n] caller index -> cluster
+  int32_t* scid;            // [n] Morton position -> cluster
+  int32_t* ucid;            // [n] unique key -> cluster
+  int32_t* croot;           // [K+1] preorder id of each cluster's root; croot[K] = node count
   double* bbox_part;        // [kBboxBlocks][6]
   int n_bbox_blocks;
   uint64_t *key_a, *key_b;  // [n]
@@ -40,6 +52,7 @@ struct BuildWs {
 hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total, hipStream_t st);
 hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st);
 hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, hipStream_t st);
+hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 
 // Tree walk launch.  Targets are processed in groups of 64 (one wavefront);
 // group g holds the targets at positions [64g, 64g+64) of `order` (Morton
@@ -49,6 +62,10 @@ struct WalkArgs {
   const void* ps;              // float4 / double4 particles in Morton order
   const int32_t* perm;         // Morton position -> caller index
   const int32_t* order;        // optional target order (Morton positions), may be null
+  const int32_t* scid;         // Morton position -> cluster
+  const int32_t* croot;        // [K+1] preorder range of each cluster's subtree
+  const int64_t* seg_off;      // [K+1] caller offsets of the clusters (list words are cluster-relative)
+  int n_seg;
   int n;
   double eps2;
   double inv_theta;            // 1/theta when theta_group is null
@@ -64,11 +81,17 @@ struct WalkArgs {
   int xcd_chunk;               // workgroups per XCD chunk of the block remap (0 = identity)
   int lds_share64;             // waves (out of 64) that read nodes through LDS copies
   int waves_per_block;         // 1, 2 or 4
+  int persistent;              // 0: one wave per group; 1: waves pull groups from `queue`
+  int32_t* queue;              // persistent: group counter, zeroed before the launch
+  int grid;                    // persistent: workgroups launched
 };
 
 enum WalkMode { kWalkForces = 0, kWalkStats = 1, kWalkDump = 2 };
 
 hipError_t launch_walk(bool f64, int mode, const WalkArgs& a, hipStream_t st);
+
+// Workgroups of the persistent walk resident on the current device at once.
+int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_per_block);
 
 // Walk copy of the nodes for one uniform theta: every record with its side l
 // replaced by S = (l/theta + s)^2 (Eq. (2) squared, the S_effective of Sec. 4.4)

@@ -121,15 +121,32 @@ hipError_t launch_mac_size(const Node* nodes, const Counts* counts, int cap, dou
 // plain node (per-group theta: S formed from l and s per lane).
 template <bool kPlain>
 struct StepNode;
+// Records are read through the constant address space: the node arrays are
+// not written while a walk runs, and saying so lets the compiler keep the
+// wave-uniform record loads on the scalar path even in loops that also store
+// results or take work from a counter.
+#define BH_CONST __attribute__((address_space(4)))
+template <typename Rec>
+__device__ __forceinline__ Rec const_load(const Rec* base, int c) {
+  const BH_CONST Rec* p = (const BH_CONST Rec*)(uintptr_t)base + c;
+  Rec r;
+  if constexpr (sizeof(Rec) == sizeof(WalkNode) && std::is_same<Rec, WalkNode>::value) {
+    r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.M = p->M; r.S = p->S; r.M32 = p->M32; r.pad = 0;
+  } else {
+    r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.M = p->M; r.l = p->l; r.s = p->s;
+  }
+  r.next = p->next; r.first = p->first; r.count = p->count; r.meta = p->meta;
+  return r;
+}
 template <>
 struct StepNode<false> {
   const WalkNode* base;
-  __device__ __forceinline__ WalkNode load(int c) const { return base[c]; }
+  __device__ __forceinline__ WalkNode load(int c) const { return const_load(base, c); }
 };
 template <>
 struct StepNode<true> {
   const Node* base;
-  __device__ __forceinline__ Node load(int c) const { return base[c]; }
+  __device__ __forceinline__ Node load(int c) const { return const_load(base, c); }
 };
 
 // One walk: a cursor over the preorder node array shared by the wave, and the
@@ -146,6 +163,8 @@ struct Cursor {
   int skip;            // the lane is active at c iff skip <= c
   int k, kend;         // position inside a leaf of several particles
   int steps;
+  int node0;           // preorder id of the root of the target's cluster (list words are relative)
+  int idx0;            // caller index of the first particle of the target's cluster
   int32_t n_pp, n_pc;
   uint64_t h;
   int64_t len;
@@ -250,7 +269,8 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64>& C, co
       }
       if (kind == 0) C.skip = nnext;
       if constexpr (kStats) {
-        const uint64_t wd = kind == 0 ? (((uint64_t)c << 1) | 1ull) : ((uint64_t)a.perm[src] << 1);
+        const uint64_t wd = kind == 0 ? (((uint64_t)(c - C.node0) << 1) | 1ull)
+                                      : ((uint64_t)(a.perm[src] - C.idx0) << 1);
         if (kind == 0) ++C.n_pc; else ++C.n_pp;
         C.h = (C.h ^ wd) * kFnvPrime;
         if (kMode == kWalkDump && C.len < a.maxlen) C.list[C.len] = (int64_t)wd;
@@ -282,25 +302,25 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 
 // The plain form: each step reads its node with scalar loads (the record is
 // wave-uniform), one round trip per step.
+// Both forms walk the subtree [C.c, end) of one cluster; `end` is clamped to
+// the node capacity, so a corrupted record can never send the cursor out of the
+// array, and every step moves the cursor forward or stays on a leaf for at most
+// its particle count.
 template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard>
-__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C) {
-  const int n_nodes = min(uniform(wn.load(0).next), 2 * a.n);
-  while (C.c < n_nodes) walk_step<kF64, kMode, kSoft, kPlain, kGuard>(a, C, wn.load(C.c));
+__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C,
+                                                 int end) {
+  while (C.c < end) walk_step<kF64, kMode, kSoft, kPlain, kGuard>(a, C, wn.load(C.c));
 }
 
 template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard>
 __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C,
-                                              uint4 (*pf)[8]) {
+                                              uint4 (*pf)[8], int end) {
   using Rec = decltype(wn.load(0));
-  // next(root) is the node count; clamp it to the capacity so that a corrupted
-  // record can never send the cursor out of the array.  Every step moves the
-  // cursor forward or stays on a leaf for at most its particle count.
   const int cap = 2 * a.n;
-  const int n_nodes = min(uniform(wn.load(0).next), cap);
   const int lane = __lane_id();
   int buf = 0, slot = 0;  // LDS buffer and slot holding the current record
-  fetch_pair(wn.base, 0, 0, lane, pf[0]);
-  while (C.c < n_nodes) {
+  fetch_pair(wn.base, C.c, C.c, lane, pf[0]);
+  while (C.c < end) {
     const int c = C.c;
     // The copy issued last step is the only vector memory operation in flight
     // here; the compiler does not order LDS-DMA writes before later LDS reads,
@@ -317,21 +337,40 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain
   }
 }
 
+// The clusters klo..khi of a wave, one subtree after the other; lanes of the
+// other clusters stay idle (skip past the subtree).
+template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kLds>
+__device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C,
+                                              uint4 (*pf)[8], bool valid, int kc, int klo, int khi) {
+  const int cap = 2 * a.n;
+  for (int k = klo; k <= khi; ++k) {
+    const int r0 = min(max(uniform(a.croot[k]), 0), cap);
+    const int r1 = min(max(uniform(a.croot[k + 1]), r0), cap);
+    C.c = r0;
+    C.k = C.kend = 0;
+    C.skip = (valid && kc == k) ? r0 : 0x7fffffff;
+    if (r0 >= r1) continue;
+    if constexpr (kLds)
+      walk_loop_lds<kF64, kMode, kSoft, kPlain, kGuard>(a, wn, C, pf, r1);
+    else
+      walk_loop_scalar<kF64, kMode, kSoft, kPlain, kGuard>(a, wn, C, r1);
+  }
+}
+
+// The walk of one group of 64 targets (one wavefront).
 // kSoft: eps > 0, so r^2 + eps^2 > 0 and the FP32 term needs no zero test.
 // kGroupTheta: theta per 64-particle Morton group instead of one uniform theta
 // (uniform theta walks the copy with S precomputed).
 template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
-__global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
+__device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (*pf)[8]) {
   using R = typename Cursor<kF64>::R;
   using R4 = typename std::conditional<kF64, double4, float4>::type;
   constexpr bool kStats = kMode != kWalkForces;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_chunk);
+  const int lane = __lane_id();
   const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
 
   Cursor<kF64> C;
-  C.slot = (blk * a.waves_per_block + wv) * kWave + lane;
+  C.slot = group * kWave + lane;
   const bool valid = C.slot < a.n;
   C.i = valid ? (a.order ? a.order[C.slot] : C.slot) : -1;
   R4 me;
@@ -345,8 +384,6 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
   C.zi = (double)me.z;
   C.inv_theta = kGroupTheta ? 1.0 / (double)a.theta_group[valid ? (C.i >> 6) : 0] : a.inv_theta;
   C.acc.init();
-  C.c = 0;
-  C.skip = valid ? 0 : 0x7fffffff;
   C.k = C.kend = 0;
   C.steps = 0;
   C.n_pp = C.n_pc = 0;
@@ -354,28 +391,43 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
   C.len = 0;
   C.list = (kMode == kWalkDump && valid) ? a.lists + (int64_t)a.perm[C.i] * a.maxlen : nullptr;
   const bool guard = ballot(valid && C.inv_theta < 1.0) != 0ull;
+  // Clusters of the wave's targets: a wave usually lies inside one cluster; one
+  // that straddles cluster edges walks each cluster's subtree in turn.
+  const int kc = valid ? min(max(a.scid[C.i], 0), a.n_seg - 1) : 0;
+  int klo = valid ? kc : 0x7fffffff, khi = valid ? kc : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    klo = min(klo, __shfl_xor(klo, o, 64));
+    khi = max(khi, __shfl_xor(khi, o, 64));
+  }
+  klo = uniform(klo);
+  khi = uniform(khi);
+  C.node0 = valid ? a.croot[kc] : 0;
+  C.idx0 = valid ? (int)a.seg_off[kc] : 0;
   StepNode<kGroupTheta> wn;
   if constexpr (kGroupTheta) wn.base = a.nodes; else wn.base = a.wnodes;
-  // per wave: two buffers of two 64-byte node records
-  __shared__ uint4 pf_lds[4][2][8];
   // Waves split between the two node paths (scalar cache / LDS copies) so
   // that neither the scalar cache nor instruction issue alone sets the pace;
   // the share taking the LDS path is a launch parameter (results identical).
-  const int wave = blk * a.waves_per_block + wv;
-  const bool lds_path = ((wave * 37) & 63) < a.lds_share64;
+  // (taken as a wave-uniform value: the compiler cannot tell that the wave
+  // index is uniform, and a branch it took for divergent would turn the walk
+  // state that crosses it into per-lane values)
+  const bool lds_path = uniform(((group * 37) & 63) < a.lds_share64 ? 1 : 0) != 0;
+  // (one cluster loop per path and guard: the LDS path's copies must not share
+  // a loop with the scalar path's loads, or the compiler stops treating the
+  // node array as unwritten and drops the scalar loads)
   if (lds_path) {
     if (guard)
-      walk_loop_lds<kF64, kMode, kSoft, kGroupTheta, true>(a, wn, C, pf_lds[wv]);
+      walk_clusters<kF64, kMode, kSoft, kGroupTheta, true, true>(a, wn, C, pf, valid, kc, klo, khi);
     else
-      walk_loop_lds<kF64, kMode, kSoft, kGroupTheta, false>(a, wn, C, pf_lds[wv]);
+      walk_clusters<kF64, kMode, kSoft, kGroupTheta, false, true>(a, wn, C, pf, valid, kc, klo, khi);
   } else {
     if (guard)
-      walk_loop_scalar<kF64, kMode, kSoft, kGroupTheta, true>(a, wn, C);
+      walk_clusters<kF64, kMode, kSoft, kGroupTheta, true, false>(a, wn, C, pf, valid, kc, klo, khi);
     else
-      walk_loop_scalar<kF64, kMode, kSoft, kGroupTheta, false>(a, wn, C);
+      walk_clusters<kF64, kMode, kSoft, kGroupTheta, false, false>(a, wn, C, pf, valid, kc, klo, khi);
   }
 
-  if (kStats && a.group_steps && lane == 0 && valid) a.group_steps[C.slot >> 6] = C.steps;
+  if (kStats && a.group_steps && lane == 0 && valid) a.group_steps[group] = C.steps;
   if (!valid) return;
   const int o = a.perm[C.i];
   R* accp = reinterpret_cast<R*>(a.acc);
@@ -391,12 +443,76 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
   }
 }
 
+// One wavefront per group; workgroups of waves_per_block waves.
+template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
+__global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
+  __shared__ uint4 pf_lds[4][2][8];  // per wave: two buffers of two 64-byte node records
+  const int wv = threadIdx.x >> 6;
+  const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_chunk);
+  // (a wave past the last target has no valid lane and walks nothing)
+  walk_group<kF64, kMode, kSoft, kGroupTheta>(a, blk * a.waves_per_block + wv, pf_lds[wv]);
+}
+
+// Persistent form: a grid that fits on the chip at once; every wave takes the
+// next group from a device counter until none is left, so the load balances
+// itself and no workgroup waits for a dispatch slot.  Every wave leaves once
+// the counter passes the last group.
+template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
+__global__ __launch_bounds__(256) void k_walk_persistent(WalkArgs a) {
+  __shared__ uint4 pf_lds[4][2][8];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int groups = (a.n + kWave - 1) / kWave;
+  for (;;) {
+    int g = 0;
+    if (lane == 0) g = atomicAdd(a.queue, 1);
+    g = __shfl(g, 0, 64);
+    if (g >= groups) break;
+    walk_group<kF64, kMode, kSoft, kGroupTheta>(a, g, pf_lds[wv]);
+  }
+}
+
 template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
 static hipError_t launch_t(const WalkArgs& a, hipStream_t st) {
   const int groups = (a.n + kWave - 1) / kWave;
   const int wpb = a.waves_per_block;
-  k_walk<kF64, kMode, kSoft, kGroupTheta><<<(groups + wpb - 1) / wpb, wpb * kWave, 0, st>>>(a);
+  const int blocks = (groups + wpb - 1) / wpb;
+  if (a.persistent) {
+    hipError_t e = fill_i32(a.queue, 1, 0, st);
+    if (e != hipSuccess) return e;
+    k_walk_persistent<kF64, kMode, kSoft, kGroupTheta><<<max(1, min(a.grid, blocks)), wpb * kWave, 0, st>>>(a);
+  } else {
+    k_walk<kF64, kMode, kSoft, kGroupTheta><<<blocks, wpb * kWave, 0, st>>>(a);
+  }
   return hipGetLastError();
+}
+
+template <bool kF64, int kMode>
+static const void* persistent_fn(bool soft, bool group_theta) {
+  if (soft)
+    return group_theta ? reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, true, true>)
+                       : reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, true, false>);
+  return group_theta ? reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, false, true>)
+                     : reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, false, false>);
+}
+
+// Workgroups of the persistent walk that are resident on the chip at once (0 if
+// the runtime cannot tell).
+int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_per_block) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* fn;
+  if (f64)
+    fn = mode == kWalkForces ? persistent_fn<true, kWalkForces>(soft, group_theta)
+       : mode == kWalkStats  ? persistent_fn<true, kWalkStats>(soft, group_theta)
+                             : persistent_fn<true, kWalkDump>(soft, group_theta);
+  else
+    fn = mode == kWalkForces ? persistent_fn<false, kWalkForces>(soft, group_theta)
+       : mode == kWalkStats  ? persistent_fn<false, kWalkStats>(soft, group_theta)
+                             : persistent_fn<false, kWalkDump>(soft, group_theta);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, waves_per_block * kWave, 0) != hipSuccess) return 0;
+  return cus * per_cu;
 }
 
 template <bool kF64, int kMode>

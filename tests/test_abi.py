@@ -57,7 +57,14 @@ def test_host_side_argument_checks():
     assert b"workspace" in lib.bh_last_error()
     assert lib.bh_forces(None, 0.5, 0.01, None, None, None) == -1
     assert lib.bh_direct(None, None, 10, 0, None, 5, -1.0, None, None, None) == -1
-    assert lib.bh_set_walk_config(None, 4, 0, 0, 0) == -1
+    assert lib.bh_set_walk_config(None, 4, 0, 0, 0, 0) == -1
+    out = ctypes.c_void_p()
+    assert lib.bh_build_forest(None, None, None, 2, 10, 0, None, 0, None, ctypes.byref(out)) == -1
+    assert lib.bh_forest_workspace_bytes(10, 0, 0) == -1
+    assert lib.bh_forest_workspace_bytes(10, 1, 0) == lib.bh_workspace_bytes(10, 0)
+    assert lib.bh_forest_workspace_bytes(10, 512, 0) > lib.bh_workspace_bytes(10, 0)
+    assert lib.bh_graph_launch(None, None) == -1
+    assert lib.bh_autotune(None, 0.5, 0.0, None, None, 1, None, None, None, 0, None) == -1
 
 
 def test_theta_bound_matches_header():

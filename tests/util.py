@@ -12,18 +12,23 @@ def force_err(acc, acc_ref, amag, kappa_max=1e3):
 
     err_i = |a_i - a_ref_i| / max(|a_ref_i|, A_i / kappa_max), A_i = sum_j |f_ij|
     the sum of the magnitudes of particle i's terms.  It is the plain relative
-    error whenever the cancellation ratio A_i/|a_i| is at most kappa_max.
+    error whenever the cancellation ratio A_i/|a_i| is at most kappa_max.  A
+    particle with no terms at all (A_i = 0, e.g. alone in its cluster) must
+    match exactly: its error is the absolute difference.
     """
     acc = widen(acc)
     acc_ref = widen(acc_ref)
     den = np.maximum(np.linalg.norm(acc_ref, axis=1), widen(amag) / kappa_max)
+    den = np.where(den > 0, den, 1.0)
     return np.linalg.norm(acc - acc_ref, axis=1) / den
 
 
 def pot_err(pot, pot_ref):
+    """Relative potential error (absolute where the reference is exactly 0)."""
     pot = widen(pot)
     pot_ref = widen(pot_ref)
-    return np.abs(pot - pot_ref) / np.abs(pot_ref)
+    den = np.abs(pot_ref)
+    return np.abs(pot - pot_ref) / np.where(den > 0, den, 1.0)
 
 
 def tree_cases():
