@@ -205,6 +205,60 @@ BH_API void bh_graph_release(bh_graph *g);
 BH_API int bh_autotune(bh_tree *t, double theta, double eps, void *acc, void *pot, int reps, void *stream,
                        bh_walk_config *best, bh_walk_config *tried, int max_tried, int *n_tried);
 
+/* ---- Learned opening parameter (beyond the paper, whose theta is one constant
+ * in Eq. (2)): per Morton group of 64 targets, features -> MLP -> theta, used
+ * by bh_forces_theta.  MLP 8 -> 64 -> 64 -> 1 with tanh-form GELU and
+ * theta = 0.2 + 0.8 sigmoid(z); matrix products in bf16 on the matrix cores
+ * with FP32 accumulation.  Parameters: flat FP32 device array of n_param = 4801
+ * values, W1 [64][8], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 (row-major);
+ * bf16 weight copies wbf16 (n_wbf16 uint16, 16-byte aligned) are made by
+ * bh_mlp_prepare and refreshed by bh_mlp_adam.  norm: FP32 [16] = mu[8],
+ * 1/sd[8]; the network sees bf16((x - mu) / sd). */
+
+/* Features of every Morton group g of t (Morton positions [64g, 64g+64); in a
+ * forest the group's cluster sets N, L and the total mass): X [ceil(n/64)][8]
+ * device FP32 = log2(h / (L (64/N)^(1/3) / 2)) with h the group's half-width,
+ * n_g / 64, log10(M_g / (M n_g / N)), RMS mass radius / h, |centre of mass -
+ * box centre| / h, log10 of the densities (M / l^3 over the mean) of the
+ * smallest cell holding the group and of its parent, log2(its side / h). */
+BH_API int bh_features(const bh_tree *t, float *X, void *stream);
+
+/* Per-group force error against a reference: for every Morton group g of t,
+ * rms[g] = RMS over its particles of |acc - acc_ref| / |acc_ref| (acc in the
+ * tree's precision, acc_ref FP64, both [n][3] caller order; a zero reference
+ * force gives inf/NaN).  If label != NULL: label[g] = max(label[g], theta)
+ * where rms[g] <= target -- called for ascending theta it leaves the largest
+ * theta of the grid that meets the target.  rms may be NULL. */
+BH_API int bh_group_error(const bh_tree *t, const void *acc, const double *acc_ref, double theta, double target,
+                          double *rms, float *label, void *stream);
+
+/* Sizes (element counts) of the MLP arrays: parameters, gradient vector (the
+ * parameters' gradient followed by the batch loss), bf16 weight copies, and
+ * the partial-gradient scratch of bh_mlp_grad for a batch of `batch` rows. */
+BH_API int bh_mlp_sizes(int64_t batch, int64_t *n_param, int64_t *n_grad, int64_t *n_wbf16, int64_t *n_partial);
+
+/* Round the weights of params to the bf16 copies wbf16. */
+BH_API int bh_mlp_prepare(const float *params, uint16_t *wbf16, void *stream);
+
+/* theta [rows] = min(alpha (0.2 + 0.8 sigmoid(z(X_row))), 1.15) for X [rows][8];
+ * a non-finite value is replaced by theta_fallback (the fixed-theta walk). */
+BH_API int bh_mlp_infer(const float *params, const uint16_t *wbf16, const float *norm, const float *X,
+                        int64_t rows, float alpha, float theta_fallback, float *theta, void *stream);
+
+/* Gradient of the loss mean_b (sigmoid(z_b) - target_b)^2 over the batch rows
+ * rows_idx [batch] of X / target (target = (theta* - 0.2) / 0.8):
+ * grad [n_grad] (device FP32, last entry = loss).  partial: scratch of
+ * n_partial floats.  Deterministic (fixed summation order). */
+BH_API int bh_mlp_grad(const float *params, const uint16_t *wbf16, const float *norm, const float *X,
+                       const float *target, const int32_t *rows_idx, int64_t batch, float *partial, float *grad,
+                       void *stream);
+
+/* One Adam step (Kingma & Ba) on params with gradient grad and moments m, v
+ * (FP32 [n_param], zero before the first step, step counts from 1); refreshes
+ * the bf16 copies. */
+BH_API int bh_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, float beta1,
+                       float beta2, float eps, uint16_t *wbf16, void *stream);
+
 /* Brute-force sum of Eq. (1) over all j != i for nt targets (Sec. 3):
  * pos [n][3], mass [n] device in precision prec; targets [nt] device int64
  * caller indices in [0, n); acc [nt][3], pot [nt] device outputs in target

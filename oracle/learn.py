@@ -8,8 +8,10 @@ the definition the GPU path is held to, written plainly in numpy.
   particles (group g = Morton positions [64g, 64g+64) of its tree):
     0  log2(h / h_typ): AABB half-width h against the half-width a group of 64
        would have in a uniform cube of the same N, h_typ = L (64/N)^(1/3) / 2
-    1  n_g / 64
-    2  log10(M_g / (M_tot n_g / N)): the group's mass against equal masses
+    1  |centre of mass - centre of mass of c| / l_c, c the smallest tree cell
+       holding the whole group, l_c its side
+    2  |centre of mass - centre of mass of a| / l_a, a the ancestor of c three
+       levels up (or the root)
     3  mass-weighted RMS radius about the group's centre of mass, over h
     4  |centre of mass - AABB centre| / h
     5  log10(rho_c / rho_mean): density M/l^3 of the smallest tree cell
@@ -134,11 +136,12 @@ def init_params(seed):
     return pack(d)
 
 
-def containing_cell(tree, a, b):
-    """Deepest node of ``tree`` (oracle.Tree) whose particle range holds Morton positions [a, b),
-    and its parent (the root is its own parent)."""
-    c, parent = 0, 0
-    while not tree.leaf[c]:
+def containing_path(tree, a, b):
+    """Root-to-leaf path of ``tree`` (oracle.Tree) down to the deepest node whose particle range
+    holds Morton positions [a, b)."""
+    path = [0]
+    while not tree.leaf[path[-1]]:
+        c = path[-1]
         ch, nxt, found = c + 1, tree.next[c], -1
         while ch < nxt:
             if tree.first[ch] <= a and tree.first[ch] + tree.count[ch] >= b:
@@ -147,8 +150,14 @@ def containing_cell(tree, a, b):
             ch = tree.next[ch]
         if found < 0:
             break
-        parent, c = c, found
-    return c, parent
+        path.append(found)
+    return path
+
+
+def containing_cell(tree, a, b):
+    """The deepest node holding [a, b) and its parent (the root is its own parent)."""
+    path = containing_path(tree, a, b)
+    return path[-1], path[-2] if len(path) > 1 else path[-1]
 
 
 def features(tree, pos, mass):
@@ -172,10 +181,13 @@ def features(tree, pos, mass):
         com = (m[:, None] * p).sum(axis=0) / M if M > 0 else gc
         r2 = ((p - com) ** 2).sum(axis=1)
         rms = np.sqrt(float((m * r2).sum()) / M) if M > 0 else 0.0
-        c, par = containing_cell(tree, a, b)
+        path = containing_path(tree, a, b)
+        c = path[-1]
+        par = path[-2] if len(path) > 1 else c
+        anc = path[-4] if len(path) > 3 else path[0]
         X[g, 0] = np.log2(h / h_typ)
-        X[g, 1] = (b - a) / 64.0
-        X[g, 2] = np.log10(max(M, 1e-300) / max(Mtot * (b - a) / n, 1e-300))
+        X[g, 1] = np.sqrt(float(((com - tree.com[c]) ** 2).sum())) / tree.l[c]
+        X[g, 2] = np.sqrt(float(((com - tree.com[anc]) ** 2).sum())) / tree.l[anc]
         X[g, 3] = rms / h
         X[g, 4] = np.sqrt(float(((com - gc) ** 2).sum())) / h
         X[g, 5] = np.log10(max(tree.M[c], 1e-300) / tree.l[c] ** 3 / rho_mean)

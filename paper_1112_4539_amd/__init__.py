@@ -70,6 +70,14 @@ def load():
         "bh_walk_time_ms": ([P, P], i32),
         "bh_tree_release": ([P], None),
         "bh_direct": ([P, P, i64, i32, P, i64, d, P, P, P], i32),
+        "bh_features": ([P, P, P], i32),
+        "bh_group_error": ([P, P, P, d, d, P, P, P], i32),
+        "bh_mlp_sizes": ([i64, P, P, P, P], i32),
+        "bh_mlp_prepare": ([P, P, P], i32),
+        "bh_mlp_infer": ([P, P, P, P, i64, ctypes.c_float, ctypes.c_float, P, P], i32),
+        "bh_mlp_grad": ([P, P, P, P, P, P, i64, P, P, P], i32),
+        "bh_mlp_adam": ([P, P, P, P, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, P],
+                        i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -209,6 +217,29 @@ class Tree:
         _check(load().bh_forest_roots(self._h, _ptr(r), _stream(self.device)))
         return r
 
+    @property
+    def n_groups(self):
+        return (self.n + 63) // 64
+
+    def features(self):
+        """Features [ceil(n/64), 8] float32 of the Morton groups (``bh_features``)."""
+        X = torch.empty((self.n_groups, 8), dtype=torch.float32, device=self.device)
+        _check(load().bh_features(self._h, _ptr(X), _stream(self.device)))
+        return X
+
+    def group_error(self, acc, acc_ref, theta=0.0, target=0.0, label=None):
+        """Per-group RMS relative force error against acc_ref (float64); optionally raises
+        label[g] to theta where it is within target (``bh_group_error``)."""
+        acc, _ = self._outs(acc, None)
+        if acc_ref.dtype != torch.float64 or acc_ref.shape != (self.n, 3) or not acc_ref.is_contiguous():
+            raise ValueError("acc_ref must be a contiguous float64 [n,3] device tensor")
+        rms = torch.empty((self.n_groups,), dtype=torch.float64, device=self.device)
+        if label is not None and (label.dtype != torch.float32 or label.shape != (self.n_groups,)):
+            raise ValueError("label must be float32 [n_groups]")
+        _check(load().bh_group_error(self._h, _ptr(acc), _ptr(acc_ref), float(theta), float(target), _ptr(rms),
+                                     _ptr(label), _stream(self.device)))
+        return rms
+
     def graph(self, theta, eps, acc, pot):
         """Capture build + forces into acc/pot as one HIP graph (``bh_graph_create``)."""
         return Graph(self, theta, eps, acc, pot)
@@ -307,6 +338,58 @@ class Graph:
 
 
 Forest = Tree
+
+
+class MLP:
+    """Parameters and kernels of the opening-parameter network (``bh_mlp_*``).
+
+    ``params`` FP32 [4801] (W1, b1, W2, b2, w3, b3), ``norm`` FP32 [16] (mu, 1/sd), bf16
+    weight copies kept in step by ``prepare`` / ``adam``.
+    """
+
+    def __init__(self, params, norm, device="cuda"):
+        lib = load()
+        npar, ngrad, nwb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.bh_mlp_sizes(1, ctypes.byref(npar), ctypes.byref(ngrad), ctypes.byref(nwb), None))
+        self.n_param, self.n_grad = npar.value, ngrad.value
+        self.device = torch.device(device)
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
+        self.norm = torch.as_tensor(norm, dtype=torch.float32).to(self.device).contiguous()
+        if self.params.shape != (self.n_param,) or self.norm.shape != (16,):
+            raise ValueError(f"params must be [{self.n_param}] and norm [16]")
+        self.wbf16 = torch.zeros((nwb.value,), dtype=torch.int16, device=self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.prepare()
+
+    def prepare(self):
+        _check(load().bh_mlp_prepare(_ptr(self.params), _ptr(self.wbf16), _stream(self.device)))
+
+    def infer(self, X, alpha=1.0, fallback=0.5):
+        X = X.contiguous()
+        theta = torch.empty((X.shape[0],), dtype=torch.float32, device=self.device)
+        _check(load().bh_mlp_infer(_ptr(self.params), _ptr(self.wbf16), _ptr(self.norm), _ptr(X), X.shape[0],
+                                   float(alpha), float(fallback), _ptr(theta), _stream(self.device)))
+        return theta
+
+    def grad(self, X, target, rows_idx):
+        """Gradient of mean((sigmoid(z) - target)^2) over rows_idx; the last entry is the loss."""
+        lib = load()
+        part = ctypes.c_int64()
+        B = int(rows_idx.shape[0])
+        _check(lib.bh_mlp_sizes(B, None, None, None, ctypes.byref(part)))
+        partial = torch.empty((part.value,), dtype=torch.float32, device=self.device)
+        g = torch.empty((self.n_grad,), dtype=torch.float32, device=self.device)
+        _check(lib.bh_mlp_grad(_ptr(self.params), _ptr(self.wbf16), _ptr(self.norm), _ptr(X.contiguous()),
+                               _ptr(target.contiguous()), _ptr(rows_idx.to(torch.int32).contiguous()), B,
+                               _ptr(partial), _ptr(g), _stream(self.device)))
+        return g
+
+    def adam(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(load().bh_mlp_adam(_ptr(self.params), _ptr(grad), _ptr(self.m), _ptr(self.v), self.step, float(lr),
+                                  float(beta1), float(beta2), float(eps), _ptr(self.wbf16), _stream(self.device)))
 
 
 def build_tree(pos, mass, workspace=None):

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbh.so")
-SOURCES = ["bh_build.hip", "bh_walk.hip", "bh_direct.hip", "bh_api.hip"]
+SOURCES = ["bh_build.hip", "bh_walk.hip", "bh_direct.hip", "bh_learn.hip", "bh_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950:xnack-", "-O3", "-std=c++17", "-fPIC",

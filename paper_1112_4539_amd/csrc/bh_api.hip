@@ -60,6 +60,7 @@ constexpr int64_t kMaxN = int64_t(1) << 30;
 constexpr int64_t kMaxClusters = int64_t(1) << 24;
 constexpr size_t kAlign = 256;
 const double kThetaMax = 2.0 / std::sqrt(3.0);
+const double kThetaCap = 1.15;  // largest learned theta handed to the walk (below 2/sqrt(3))
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -528,6 +529,91 @@ int bh_autotune(bh_tree* t, double theta, double eps, void* acc, void* pot, int 
   (void)bh_set_timing(t, was_timing ? 1 : 0);
   if (rc != BH_OK) return rc;
   *best = cur;
+  return BH_OK;
+}
+
+/* ---- learned opening parameter */
+
+int bh_features(const bh_tree* t, float* X, void* stream) {
+  if (!t) return fail(BH_EINVAL, "null tree");
+  if (t->n == 0) return BH_OK;
+  if (!X || !aligned(X, 4)) return fail(BH_EINVAL, "X must be a non-null device array of floats");
+  hipError_t e = bh::launch_features(t->prec == BH_FP64, t->w.nodes, t->w.ps, t->w.cube, t->w.scid, t->w.croot,
+                                     t->w.seg_off, (int)t->n_seg, (int)t->n, X, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the feature pass");
+  return BH_OK;
+}
+
+int bh_group_error(const bh_tree* t, const void* acc, const double* acc_ref, double theta, double target,
+                   double* rms, float* label, void* stream) {
+  if (!t) return fail(BH_EINVAL, "null tree");
+  if (t->n == 0) return BH_OK;
+  const size_t el = t->prec == BH_FP64 ? 8 : 4;
+  if (!acc || !acc_ref || !aligned(acc, el) || !aligned(acc_ref, 8))
+    return fail(BH_EINVAL, "acc/acc_ref must be non-null aligned device arrays");
+  if ((rms && !aligned(rms, 8)) || (label && !aligned(label, 4)))
+    return fail(BH_EINVAL, "rms/label must be aligned device arrays");
+  hipError_t e = bh::launch_group_error(t->prec == BH_FP64, acc, acc_ref, t->w.idx_a, (int)t->n, theta, target, rms,
+                                        label, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the group error pass");
+  return BH_OK;
+}
+
+int bh_mlp_sizes(int64_t batch, int64_t* n_param, int64_t* n_grad, int64_t* n_wbf16, int64_t* n_partial) {
+  if (batch < 0 || batch > kMaxN) return fail(BH_EINVAL, "batch must be in [0, 2^30]");
+  if (n_param) *n_param = bh::kMlpParams;
+  if (n_grad) *n_grad = bh::kMlpGradLen;
+  if (n_wbf16) *n_wbf16 = bh::kMlpWb;
+  if (n_partial) *n_partial = (int64_t)bh::mlp_grad_parts((int)(batch > 0 ? batch : 1)) * bh::kMlpGradLen;
+  return BH_OK;
+}
+
+int bh_mlp_prepare(const float* params, uint16_t* wbf16, void* stream) {
+  if (!params || !wbf16 || !aligned(params, 4) || !aligned(wbf16, 16))
+    return fail(BH_EINVAL, "params (4-byte) and wbf16 (16-byte aligned) must be device arrays");
+  hipError_t e = bh::launch_mlp_prepare(params, wbf16, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the weight copy");
+  return BH_OK;
+}
+
+int bh_mlp_infer(const float* params, const uint16_t* wbf16, const float* norm, const float* X, int64_t rows,
+                 float alpha, float theta_fallback, float* theta, void* stream) {
+  if (rows < 0 || rows > kMaxN) return fail(BH_EINVAL, "rows must be in [0, 2^30]");
+  if (rows == 0) return BH_OK;
+  if (!params || !wbf16 || !norm || !X || !theta || !aligned(wbf16, 16) || !aligned(X, 4) || !aligned(theta, 4))
+    return fail(BH_EINVAL, "null or misaligned device array");
+  if (!(alpha > 0.f) || !std::isfinite(alpha)) return fail(BH_EINVAL, "alpha must be finite and > 0");
+  if (!(theta_fallback > 0.f && theta_fallback < kThetaMax))
+    return fail(BH_EINVAL, "theta_fallback must be in (0, 2/sqrt(3))");
+  hipError_t e = bh::launch_mlp_infer(params, wbf16, norm, X, rows, alpha, theta_fallback, (float)kThetaCap, theta,
+                                      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the MLP");
+  return BH_OK;
+}
+
+int bh_mlp_grad(const float* params, const uint16_t* wbf16, const float* norm, const float* X, const float* target,
+                const int32_t* rows_idx, int64_t batch, float* partial, float* grad, void* stream) {
+  if (batch < 1 || batch > kMaxN) return fail(BH_EINVAL, "batch must be in [1, 2^30]");
+  if (!params || !wbf16 || !norm || !X || !target || !rows_idx || !partial || !grad || !aligned(wbf16, 16) ||
+      !aligned(rows_idx, 4) || !aligned(partial, 4) || !aligned(grad, 4))
+    return fail(BH_EINVAL, "null or misaligned device array");
+  hipError_t e = bh::launch_mlp_grad(params, wbf16, norm, X, target, rows_idx, (int)batch, partial, grad,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the MLP gradient");
+  return BH_OK;
+}
+
+int bh_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                float beta2, float eps, uint16_t* wbf16, void* stream) {
+  if (!params || !grad || !m || !v || !wbf16 || !aligned(wbf16, 16)) return fail(BH_EINVAL, "null device array");
+  if (step < 1) return fail(BH_EINVAL, "step counts from 1");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(BH_EINVAL, "invalid Adam hyper-parameters");
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  hipError_t e = bh::launch_mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, c1, c2, wbf16,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the Adam step");
   return BH_OK;
 }
 

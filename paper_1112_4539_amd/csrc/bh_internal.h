@@ -99,6 +99,30 @@ int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_p
 hipError_t launch_mac_size(const Node* nodes, const Counts* counts, int cap, double inv_theta,
                            WalkNode* wnodes, hipStream_t st);
 
+// ---- learned opening parameter (bh_learn.hip)
+// Flat FP32 parameters of the MLP 8 -> 64 -> 64 -> 1: W1 [64][8], b1 [64],
+// W2 [64][64], b2 [64], w3 [64], b3; a gradient vector has one more entry
+// (the batch loss).  bf16 weight copies: W1, W2, W2 transposed, w3.
+constexpr int kMlpW1 = 0, kMlpB1 = 512, kMlpW2 = 576, kMlpB2 = 4672, kMlpw3 = 4736, kMlpB3 = 4800;
+constexpr int kMlpParams = 4801;
+constexpr int kMlpGradLen = kMlpParams + 1;
+constexpr int kMlpW1b = 0, kMlpW2b = 512, kMlpW2Tb = 4608, kMlpw3b = 8704, kMlpWb = 8768;
+constexpr int kMlpMaxParts = 1024;  // workgroups (partial gradients) of one gradient pass
+
+hipError_t launch_features(bool f64, const Node* nodes, const void* ps, const Cube* cubes, const int32_t* scid,
+                           const int32_t* croot, const int64_t* seg_off, int n_seg, int n, float* X,
+                           hipStream_t st);
+hipError_t launch_group_error(bool f64, const void* acc, const double* ref, const int32_t* perm, int n,
+                              double theta, double target, double* rms, float* label, hipStream_t st);
+hipError_t launch_mlp_prepare(const float* P, uint16_t* wb, hipStream_t st);
+hipError_t launch_mlp_infer(const float* P, const uint16_t* wb, const float* norm, const float* X, int64_t rows,
+                            float alpha, float fallback, float cap, float* theta, hipStream_t st);
+int mlp_grad_parts(int batch);
+hipError_t launch_mlp_grad(const float* P, const uint16_t* wb, const float* norm, const float* X, const float* T,
+                           const int32_t* idx, int batch, float* partial, float* grad, hipStream_t st);
+hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
+                           float eps, float c1, float c2, uint16_t* wb, hipStream_t st);
+
 // Direct sum of Eq. (1) for a list of targets (caller indices).
 hipError_t launch_direct(bool f64, const void* pos, const void* mass, int n, const int64_t* targets, int nt,
                          double eps, void* acc, void* pot, hipStream_t st);

@@ -1,0 +1,178 @@
+"""Learned opening parameter: labelling, training and use of the theta network.
+
+Host orchestration only: every number is computed by the library's kernels
+(features, direct sum, force walks, per-group errors, the MLP's forward,
+gradient and Adam passes); this module chooses what to run.  The two pieces
+of host arithmetic are the feature normalisation constants (eight means and
+standard deviations of the training features) and the minibatch shuffles.
+
+Labels: a training snapshot is walked at every theta of the grid 0.20, 0.25,
+..., 1.00; for every Morton group g of 64 targets this gives its RMS relative
+force error R[k, g] against the FP64 direct sum and its cost C[k, g] (nodes its
+wavefront visits).  The label is the cost-optimal allocation for the snapshot:
+theta*_g = grid[argmin_k C[k, g] + lambda n_g R[k, g]^2], with the multiplier
+lambda bisected so that the snapshot's overall RMS error is the target (1e-3)
+-- the least total cost at that error that per-group choices on the grid can
+reach.  (Labelling each group with the largest theta that keeps its own error
+within the target spends interactions where they buy little accuracy.)  The
+network is fitted to t = (theta* - 0.2) / 0.8 with the loss
+mean((sigmoid(z) - t)^2).  At use, theta_g = min(alpha * theta(x_g),
+1.15), with alpha a single scale that the caller sets (e.g. by bisection to a
+global error target); a non-finite output falls back to a fixed theta.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+import paper_1112_4539_amd as bh
+from paper_1112_4539_amd import inputs
+
+THETA_GRID = tuple(round(0.20 + 0.05 * k, 2) for k in range(17))
+TARGET = 1e-3
+N_PARAM = 4801
+
+
+def init_params(seed):
+    """Uniform(+-1/sqrt(fan_in)) weights, zero biases, in the flat layout W1, b1, W2, b2, w3, b3."""
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.uniform(-1, 1, 512) / math.sqrt(8), np.zeros(64),
+                           rng.uniform(-1, 1, 4096) / math.sqrt(64), np.zeros(64),
+                           rng.uniform(-1, 1, 64) / math.sqrt(64), np.zeros(1)]).astype(np.float32)
+
+
+def _dev(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def allocate(R, C, n_g, target):
+    """Cost-optimal grid index per group: argmin_k C[k,g] + lam n_g R[k,g]^2 with lam such that
+    sqrt(sum_g n_g R[k_g,g]^2 / N) is at most (and close to) the target."""
+    E = n_g[None, :] * R * R
+    N = float(n_g.sum())
+    cols = np.arange(R.shape[1])
+
+    def pick(lam):
+        k = np.argmin(C + lam * E, axis=0)
+        return k, np.sqrt(E[k, cols].sum() / N)
+
+    lo, hi = 0.0, 40.0      # log10 of lambda
+    k, err = pick(10.0 ** hi)
+    if err > target:
+        return k
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        km, em = pick(10.0 ** mid)
+        if em <= target:
+            hi, k = mid, km
+        else:
+            lo = mid
+    return k
+
+
+def label_snapshot(pos, mass, eps, grid=THETA_GRID, target=TARGET):
+    """Features [G, 8] and labels [G] (device float32) of one particle set (FP32 walk), plus the
+    per-group error and cost tables R, C [len(grid), G]."""
+    gp, gm = _dev(pos, torch.float32), _dev(mass, torch.float32)
+    T = bh.Tree(gp, gm)
+    X = T.features()
+    # the reference sees exactly the FP32 values the walk sees
+    a_ref, _ = bh.direct(gp.double(), gm.double(), eps)
+    R, C = [], []
+    for th in grid:
+        st = T.walk_stats(th, eps)
+        R.append(T.group_error(st["acc"], a_ref))
+        C.append(st["group_steps"].double())
+    R = torch.stack(R).cpu().numpy()
+    C = torch.stack(C).cpu().numpy()
+    n_g = np.full(T.n_groups, 64.0)
+    n_g[-1] = T.n - 64 * (T.n_groups - 1)
+    k = allocate(R, C, n_g, target)
+    label = torch.tensor(np.asarray(grid, np.float32)[k], device="cuda")
+    return X, label, R, C
+
+
+def training_snapshot(seed, n=262_144):
+    """Training set member: even seeds a Plummer sphere (eps 0.005), odd seeds the clumpy field
+    recipe (25% uniform + 64 clumps, eps 1e-4)."""
+    if seed % 2 == 0:
+        pos, mass = inputs.plummer(n, seed)
+        return pos, mass, 0.005
+    pos, mass = inputs.clumpy(n, seed)
+    return pos, mass, 1e-4
+
+
+def build_dataset(seeds, n=262_144, log=None):
+    Xs, Ls = [], []
+    for s in seeds:
+        pos, mass, eps = training_snapshot(s, n)
+        X, lab, _, _ = label_snapshot(pos, mass, eps)
+        Xs.append(X)
+        Ls.append(lab)
+        if log:
+            log(f"[learn] snapshot seed={s} n={n} groups={len(lab)} mean label={float(lab.mean()):.3f}")
+    return torch.cat(Xs), torch.cat(Ls)
+
+
+def fit_norm(X):
+    x = X.double().cpu().numpy()
+    mu = x.mean(axis=0)
+    sd = x.std(axis=0)
+    sd = np.where(sd > 1e-6, sd, 1.0)
+    return np.concatenate([mu, 1.0 / sd]).astype(np.float32)
+
+
+def train(X, labels, epochs=40, batch=4096, lr=3e-3, lr_end=3e-4, seed=0, log=None):
+    """Fit the network with Adam on minibatches; returns (MLP, per-epoch mean loss)."""
+    net = bh.MLP(init_params(seed), fit_norm(X))
+    t = ((labels - 0.2) / 0.8).contiguous()
+    R = X.shape[0]
+    rng = np.random.default_rng(seed)
+    steps_per_epoch = max(1, R // batch)
+    total = epochs * steps_per_epoch
+    history = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(R).astype(np.int32), device="cuda")
+        losses = []
+        for b in range(steps_per_epoch):
+            g = net.grad(X, t, perm[b * batch:(b + 1) * batch])
+            # cosine decay from lr to lr_end
+            lr_s = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * step / max(1, total - 1)))
+            net.adam(g, lr_s)
+            losses.append(g[-1:])
+            step += 1
+        history.append(float(torch.cat(losses).mean().item()))
+        if log and (ep % 10 == 0 or ep == epochs - 1):
+            log(f"[learn] epoch {ep} loss {history[-1]:.5f}")
+    return net, history
+
+
+def rms_error(acc, a_ref, targets):
+    """RMS of |a - a_ref| / |a_ref| over the sampled targets (a_ref float64 [len(targets), 3])."""
+    d = (acc[targets].double() - a_ref).norm(dim=1) / a_ref.norm(dim=1)
+    return float(torch.sqrt(torch.mean(d * d)).item())
+
+
+def bisect(f, lo, hi, target, rel=0.02, iters=40):
+    """Largest x in [lo, hi] with f(x) <= target, f increasing; stops within rel of the target.
+    Returns (x, f(x))."""
+    flo = f(lo)
+    if flo > target:
+        return lo, flo
+    fhi = f(hi)
+    if fhi <= target:
+        return hi, fhi
+    best = (lo, flo)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        fm = f(mid)
+        if fm <= target:
+            lo, best = mid, (mid, fm)
+            if fm >= target * (1 - rel):
+                break
+        else:
+            hi = mid
+    return best

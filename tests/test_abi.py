@@ -64,6 +64,12 @@ def test_host_side_argument_checks():
     assert lib.bh_forest_workspace_bytes(10, 1, 0) == lib.bh_workspace_bytes(10, 0)
     assert lib.bh_forest_workspace_bytes(10, 512, 0) > lib.bh_workspace_bytes(10, 0)
     assert lib.bh_graph_launch(None, None) == -1
+    n_param, n_grad, n_wb, n_part = (ctypes.c_int64() for _ in range(4))
+    assert lib.bh_mlp_sizes(4096, ctypes.byref(n_param), ctypes.byref(n_grad), ctypes.byref(n_wb),
+                            ctypes.byref(n_part)) == 0
+    assert (n_param.value, n_grad.value, n_wb.value) == (4801, 4802, 8768)
+    assert n_part.value == 128 * 4802
+    assert lib.bh_mlp_infer(None, None, None, None, 10, ctypes.c_float(1.0), ctypes.c_float(0.5), None, None) == -1
     assert lib.bh_autotune(None, 0.5, 0.0, None, None, 1, None, None, None, 0, None) == -1
 
 

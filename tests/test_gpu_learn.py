@@ -1,0 +1,153 @@
+"""GPU parity of the learned opening parameter against the CPU oracle (oracle/learn.py).
+
+Features and per-group errors follow FP64 definitions (tight tolerances); the
+MLP's forward, gradient and Adam passes are held to the oracle with the same
+bf16 rounding points (FP32 accumulation on the GPU against FP64 in the
+oracle: a rounding point can flip by one bf16 ulp, hence the norm-wise bound
+of 1e-3 per gradient tensor).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import learn as olearn
+from paper_1112_4539_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bh():
+    import paper_1112_4539_amd as bh
+    bh.load()
+    assert torch.cuda.is_available()
+    return bh
+
+
+@pytest.mark.parametrize("which,prec", [("plummer", "fp64"), ("plummer", "fp32"), ("clumpy", "fp32")])
+def test_features_match_oracle(bh, which, prec):
+    say(f"[learn] features {which} {prec}")
+    if which == "plummer":
+        pos, mass = inputs.plummer(20_011, 31)
+        mass = mass * np.random.default_rng(3).uniform(0.5, 1.5, len(mass))
+    else:
+        pos, mass = inputs.clumpy(50_000, 33)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    npdt = np.float32 if prec == "fp32" else np.float64
+    T = bh.Tree(torch.tensor(pos, dtype=dt, device="cuda"), torch.tensor(mass, dtype=dt, device="cuda"))
+    X = T.features().cpu().numpy().astype(np.float64)
+    p64, m64 = pos.astype(npdt).astype(np.float64), mass.astype(npdt).astype(np.float64)
+    Xo = olearn.features(oracle.Tree(p64, m64), p64, m64)
+    assert X.shape == Xo.shape
+    np.testing.assert_allclose(X, Xo, rtol=2e-6, atol=2e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_group_error_and_labels(bh, prec):
+    say(f"[learn] group error {prec}")
+    pos, mass = inputs.plummer(9_000, 35)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    T = bh.Tree(torch.tensor(pos, dtype=dt, device="cuda"), torch.tensor(mass, dtype=dt, device="cuda"))
+    rng = np.random.default_rng(5)
+    ref = rng.normal(size=(len(pos), 3))
+    acc = ref * (1 + rng.normal(0, 1e-3, (len(pos), 1)))
+    label = torch.full((T.n_groups,), 0.2, dtype=torch.float32, device="cuda")
+    rms = T.group_error(torch.tensor(acc, dtype=dt, device="cuda"), torch.tensor(ref, device="cuda"), 0.45, 1e-3,
+                        label)
+    _, perm = T.export()
+    acc_seen = acc.astype(np.float32 if prec == "fp32" else np.float64)
+    want = olearn.group_rms(acc_seen, ref, perm)
+    np.testing.assert_allclose(rms.cpu().numpy(), want, rtol=1e-12)
+    np.testing.assert_array_equal(label.cpu().numpy(), np.where(want <= 1e-3, np.float32(0.45), np.float32(0.2)))
+
+
+def _net_problem(rows, seed):
+    rng = np.random.default_rng(seed)
+    P = olearn.init_params(seed).astype(np.float32)
+    P[512:576] = rng.normal(0, 0.3, 64)
+    P[4672:4736] = rng.normal(0, 0.3, 64)
+    P[4800] = 0.3
+    X = (rng.normal(0, 2, (rows, 8)) + 1.0).astype(np.float32)
+    norm = np.concatenate([rng.normal(1, 0.1, 8), rng.uniform(0.3, 0.7, 8)]).astype(np.float32)
+    t = rng.uniform(0, 1, rows).astype(np.float32)
+    return P, X, norm, t
+
+
+def test_mlp_forward_matches_oracle(bh):
+    say("[learn] mlp forward")
+    P, X, norm, _ = _net_problem(1000, 1)          # ragged: 31.25 tiles of 32 rows
+    net = bh.MLP(P, norm)
+    th = net.infer(torch.tensor(X, device="cuda")).cpu().numpy().astype(np.float64)
+    f = olearn.forward(P.astype(np.float64), X, norm[:8].astype(np.float64), norm[8:].astype(np.float64))
+    d = np.abs(th - f["theta"])
+    say(f"  max |dtheta| {d.max():.2e}  median {np.median(d):.2e}")
+    assert d.max() <= 1e-3 and np.median(d) <= 1e-5
+    # alpha scales, the cap holds, non-finite parameters fall back
+    th2 = net.infer(torch.tensor(X, device="cuda"), alpha=1.5).cpu().numpy()
+    np.testing.assert_allclose(th2, np.minimum(np.float32(1.5) * th.astype(np.float32), np.float32(1.15)), rtol=1e-6)
+    Pbad = P.copy()
+    Pbad[4800] = np.nan
+    bad = bh.MLP(Pbad, norm).infer(torch.tensor(X, device="cuda"), fallback=0.45).cpu().numpy()
+    assert np.all(bad == np.float32(0.45))
+
+
+@pytest.mark.parametrize("batch", [4096, 1000, 7])
+def test_mlp_gradient_matches_oracle(bh, batch):
+    say(f"[learn] mlp gradient batch={batch}")
+    P, X, norm, t = _net_problem(6000, 2)
+    rng = np.random.default_rng(9)
+    idx = np.sort(rng.choice(len(X), batch, replace=False)).astype(np.int32)
+    net = bh.MLP(P, norm)
+    g = net.grad(torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda"),
+                 torch.tensor(idx, device="cuda")).cpu().numpy().astype(np.float64)
+    loss, go = olearn.loss_and_grad(P.astype(np.float64), X[idx], t[idx], norm[:8].astype(np.float64),
+                                    norm[8:].astype(np.float64))
+    assert abs(g[-1] - loss) <= 1e-5 * loss
+    for name, (o, s) in olearn.LAYOUT.items():
+        sl = slice(o, o + int(np.prod(s)))
+        err = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
+        say(f"  {name}: rel err {err:.2e}")
+        assert err <= 1e-3, name
+
+
+def test_adam_matches_oracle(bh):
+    say("[learn] adam")
+    P, X, norm, t = _net_problem(2048, 3)
+    net = bh.MLP(P, norm)
+    Xd, td = torch.tensor(X, device="cuda"), torch.tensor(t, device="cuda")
+    idx = torch.arange(2048, dtype=torch.int32, device="cuda")
+    Po = P.astype(np.float64)
+    m = np.zeros_like(Po)
+    v = np.zeros_like(Po)
+    for step in range(1, 4):
+        g = net.grad(Xd, td, idx)
+        gh = g[:-1].cpu().numpy().astype(np.float64)
+        net.adam(g, 1e-3)
+        Po, m, v = olearn.adam(Po, gh, m, v, step, 1e-3)
+        # the oracle steps from the GPU's own parameters (fp32), so only the step is compared
+        got = net.params.cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(got, Po, rtol=1e-6, atol=1e-7)
+        Po = got.copy()
+
+
+def test_training_reduces_loss(bh):
+    """A learnable target (a smooth function of the features) is fitted by the GPU training loop."""
+    say("[learn] training")
+    from paper_1112_4539_amd import learn
+    rng = np.random.default_rng(11)
+    X = rng.normal(0, 1, (16384, 8)).astype(np.float32)
+    th = 0.2 + 0.8 / (1 + np.exp(-(1.5 * X[:, 0] - X[:, 3] + 0.5 * X[:, 5] * X[:, 6])))
+    net, hist = learn.train(torch.tensor(X, device="cuda"), torch.tensor(th.astype(np.float32), device="cuda"),
+                            epochs=30, batch=1024, lr=3e-3)
+    say(f"  loss {hist[0]:.4f} -> {hist[-1]:.5f}")
+    assert hist[-1] < 0.1 * hist[0]
+    pred = net.infer(torch.tensor(X, device="cuda")).cpu().numpy()
+    assert np.sqrt(np.mean((pred - th) ** 2)) < 0.05

@@ -122,8 +122,6 @@ def test_features_lattice():
     L = T.L
     h = 1.5 * s
     np.testing.assert_allclose(X[:, 0], np.log2(h / (0.5 * L * (64 / 4096) ** (1 / 3))), rtol=1e-12)
-    np.testing.assert_allclose(X[:, 1], 1.0)
-    np.testing.assert_allclose(X[:, 2], 0.0, atol=1e-12)
     np.testing.assert_allclose(X[:, 3], np.sqrt(3 * 1.25) * s / h, rtol=1e-12)
     np.testing.assert_allclose(X[:, 4], 0.0, atol=1e-12)
 
@@ -148,6 +146,12 @@ def test_features_cells_brute_force():
         ps = pos[T.perm[a:b]]
         h = max(np.max(ps.max(0) - ps.min(0)) / 2, T.L * 2.0 ** -22)
         np.testing.assert_allclose(X[g, 7], np.log2(T.l[c] / h), rtol=1e-12)
+        ancestors = sorted([p for p in holds if p != c], key=lambda k: T.level[k])
+        anc = ancestors[-3] if len(ancestors) >= 3 else 0
+        w = mass[T.perm[a:b]]
+        com = (w[:, None] * ps).sum(0) / w.sum()
+        np.testing.assert_allclose(X[g, 1], np.linalg.norm(com - T.com[c]) / T.l[c], rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(X[g, 2], np.linalg.norm(com - T.com[anc]) / T.l[anc], rtol=1e-9, atol=1e-12)
 
 
 def test_group_rms_definition():
