@@ -160,6 +160,7 @@ def main():
     ap.add_argument("--target-order", type=int, default=0)
     ap.add_argument("--lds-share", type=int, default=16)
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--targets-per-lane", type=int, default=1)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -200,7 +201,7 @@ def main():
     def step():
         T = bh.Tree(gpos, gmass, workspace=ws)
         T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share,
-                          args.persistent)
+                          args.persistent, args.targets_per_lane)
         T.forces(args.theta, eps, acc=acc, pot=pot)
         return T
 
@@ -229,7 +230,7 @@ def main():
     for _ in range(args.steps):
         T = bh.Tree(gpos, gmass, workspace=ws)
         T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share,
-                          args.persistent)
+                          args.persistent, args.targets_per_lane)
         T.set_timing(True)
         T.forces(args.theta, eps, acc=acc, pot=pot)
         walk_ms.append(T)
@@ -288,7 +289,7 @@ def main():
             "n_nodes": tstats["n_nodes"],
             "launch": {"waves_per_block": args.waves_per_block, "xcd_chunk": args.xcd_chunk,
                        "target_order": args.target_order, "lds_share": args.lds_share,
-                       "persistent": args.persistent},
+                       "persistent": args.persistent, "targets_per_lane": args.targets_per_lane},
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

@@ -53,6 +53,7 @@ typedef struct bh_walk_config {
   int xcd_chunk;
   int lds_share;
   int persistent;
+  int targets_per_lane;
   float ms;
 } bh_walk_config;
 
@@ -146,9 +147,12 @@ BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *st
  * persistent 0 = one wavefront per group of 64 targets, 1 = a grid that fits
  * the chip at once whose wavefronts take groups from a device counter (kept in
  * the workspace: two walks of one tree must not run concurrently).
+ * targets_per_lane 1 or 2: a wavefront walks 64 or 128 Morton-consecutive
+ * targets (each node record it reads serves twice as many targets; group_steps
+ * of bh_walk_stats then gives each 64-target group its wavefront's count).
  * Results do not depend on any of them. */
 BH_API int bh_set_walk_config(bh_tree *t, int waves_per_block, int xcd_chunk, int target_order,
-                              int lds_share, int persistent);
+                              int lds_share, int persistent, int targets_per_lane);
 
 /* Enable (1) or disable (0) HIP-event timing of the walk kernel; after a
  * timed walk, bh_walk_time_ms synchronises and returns its duration. */
@@ -197,8 +201,8 @@ BH_API int bh_graph_launch(bh_graph *g, void *stream);
 BH_API void bh_graph_release(bh_graph *g);
 
 /* Pick the walk shape of t by measurement: runs bh_forces (theta, eps, acc, pot)
- * reps times per candidate, one knob at a time (persistent, waves_per_block,
- * lds_share, xcd_chunk), keeps the fastest (HIP-event walk time, best of reps),
+ * reps times per candidate, one knob at a time (targets_per_lane, persistent,
+ * waves_per_block, lds_share, xcd_chunk), keeps the fastest (HIP-event walk time, best of reps),
  * sets it on t and returns it in *best.  If tried != NULL the first max_tried
  * candidates measured are written there and *n_tried gets their number.
  * Synchronises the stream; results of the walk do not depend on the choice. */

@@ -32,7 +32,7 @@ class BHError(RuntimeError):
 class WalkConfig(ctypes.Structure):
     """``bh_walk_config``: a launch shape of the walk and its measured time."""
     _fields_ = [("waves_per_block", ctypes.c_int), ("xcd_chunk", ctypes.c_int), ("lds_share", ctypes.c_int),
-                ("persistent", ctypes.c_int), ("ms", ctypes.c_float)]
+                ("persistent", ctypes.c_int), ("targets_per_lane", ctypes.c_int), ("ms", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +65,7 @@ def load():
         "bh_forces_theta": ([P, P, d, P, P, P], i32),
         "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P, P], i32),
         "bh_tree_export": ([P, P, P, P], i32),
-        "bh_set_walk_config": ([P, i32, i32, i32, i32, i32], i32),
+        "bh_set_walk_config": ([P, i32, i32, i32, i32, i32, i32], i32),
         "bh_set_timing": ([P, i32], i32),
         "bh_walk_time_ms": ([P, P], i32),
         "bh_tree_release": ([P], None),
@@ -196,9 +196,10 @@ class Tree:
                                     ctypes.byref(c)))
         return dict(n_nodes=a.value, n_leaves=b.value, n_internal=c.value)
 
-    def set_walk_config(self, waves_per_block=4, xcd_chunk=0, target_order=0, lds_share=16, persistent=0):
+    def set_walk_config(self, waves_per_block=4, xcd_chunk=0, target_order=0, lds_share=16, persistent=0,
+                        targets_per_lane=1):
         _check(load().bh_set_walk_config(self._h, int(waves_per_block), int(xcd_chunk), int(target_order),
-                                         int(lds_share), int(persistent)))
+                                         int(lds_share), int(persistent), int(targets_per_lane)))
 
     def autotune(self, theta, eps, acc=None, pot=None, reps=2, max_tried=64):
         """Pick the walk shape by measurement (``bh_autotune``); returns (best, tried) as dicts."""

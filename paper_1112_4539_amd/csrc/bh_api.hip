@@ -30,6 +30,7 @@ struct bh_tree {
   int target_order = 0;
   int lds_share64 = 16;
   int persistent = 0;
+  int targets_per_lane = 1;
   bool timing = false;
   bool timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -198,9 +199,11 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.lds_share64 = t->lds_share64;
   a.waves_per_block = t->waves_per_block;
   a.persistent = t->persistent;
+  a.targets_per_lane = t->targets_per_lane;
   a.queue = t->queue;
   if (t->persistent) {
-    a.grid = bh::persistent_grid(t->prec == BH_FP64, mode, eps * eps > 0.0, theta_group != nullptr, t->waves_per_block);
+    a.grid = bh::persistent_grid(t->prec == BH_FP64, mode, eps * eps > 0.0, theta_group != nullptr, t->waves_per_block,
+                                 t->targets_per_lane);
     if (a.grid <= 0) return fail(BH_EHIP, "cannot size the persistent walk grid");
   }
   bh_tree* mt = const_cast<bh_tree*>(t);
@@ -225,7 +228,7 @@ extern "C" {
 
 const char* bh_last_error(void) { return g_err; }
 
-int bh_version(void) { return 1; }
+int bh_version(void) { return 2; }
 
 int64_t bh_forest_workspace_bytes(int64_t n, int64_t n_clusters, int prec) {
   if (n < 0 || n > kMaxN || n_clusters < 1 || n_clusters > kMaxClusters || (prec != BH_FP32 && prec != BH_FP64))
@@ -336,7 +339,7 @@ int bh_tree_export(const bh_tree* t, void* nodes, int32_t* perm, void* stream) {
 }
 
 int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int target_order, int lds_share,
-                       int persistent) {
+                       int persistent, int targets_per_lane) {
   if (!t) return fail(BH_EINVAL, "null tree");
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(BH_EINVAL, "waves_per_block must be 1, 2 or 4");
@@ -344,8 +347,10 @@ int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int targe
   if (target_order != 0 && target_order != 1) return fail(BH_EINVAL, "target_order must be 0 or 1");
   if (lds_share < 0 || lds_share > 64) return fail(BH_EINVAL, "lds_share must be in [0, 64]");
   if (persistent != 0 && persistent != 1) return fail(BH_EINVAL, "persistent must be 0 or 1");
+  if (targets_per_lane != 1 && targets_per_lane != 2) return fail(BH_EINVAL, "targets_per_lane must be 1 or 2");
   t->lds_share64 = lds_share;
   t->persistent = persistent;
+  t->targets_per_lane = targets_per_lane;
   t->waves_per_block = waves_per_block;
   t->xcd_chunk = xcd_chunk;
   t->target_order = target_order;
@@ -481,12 +486,13 @@ int bh_autotune(bh_tree* t, double theta, double eps, void* acc, void* pot, int 
   if (n_tried) *n_tried = 0;
   const bool was_timing = t->timing;
   if ((rc = bh_set_timing(t, 1)) != BH_OK) return rc;
-  bh_walk_config cur{t->waves_per_block, t->xcd_chunk, t->lds_share64, t->persistent, 0.f};
+  bh_walk_config cur{t->waves_per_block, t->xcd_chunk, t->lds_share64, t->persistent, t->targets_per_lane, 0.f};
   auto measure = [&](bh_walk_config& c) -> int {
     t->waves_per_block = c.waves_per_block;
     t->xcd_chunk = c.xcd_chunk;
     t->lds_share64 = c.lds_share;
     t->persistent = c.persistent;
+    t->targets_per_lane = c.targets_per_lane;
     float bestms = 0.f;
     for (int r = 0; r < reps; ++r) {
       int q = bh_forces(t, theta, eps, acc, pot, stream);
@@ -502,19 +508,21 @@ int bh_autotune(bh_tree* t, double theta, double eps, void* acc, void* pot, int 
   };
   // coordinate search: one knob at a time, keeping the best so far
   if ((rc = measure(cur)) != BH_OK) return rc;
+  static const int kTargets[] = {1, 2};
   static const int kPersistent[] = {0, 1};
   static const int kWpb[] = {1, 2, 4};
   static const int kShare[] = {0, 8, 16, 32};
   static const int kChunk[] = {0, 2, 8};
-  for (int stage = 0; stage < 4 && rc == BH_OK; ++stage) {
-    const int* vals = stage == 0 ? kPersistent : stage == 1 ? kWpb : stage == 2 ? kShare : kChunk;
-    const int nv = stage == 0 ? 2 : stage == 1 ? 3 : stage == 2 ? 4 : 3;
-    if (stage == 3 && cur.persistent) break;  // the block remap does not apply to the persistent walk
+  for (int stage = 0; stage < 5 && rc == BH_OK; ++stage) {
+    const int* vals = stage == 0 ? kTargets : stage == 1 ? kPersistent : stage == 2 ? kWpb : stage == 3 ? kShare
+                                                                                                        : kChunk;
+    const int nv = stage == 0 ? 2 : stage == 1 ? 2 : stage == 2 ? 3 : stage == 3 ? 4 : 3;
+    if (stage == 4 && cur.persistent) break;  // the block remap does not apply to the persistent walk
     bh_walk_config stage_best = cur;
     for (int v = 0; v < nv; ++v) {
       bh_walk_config c = cur;
-      int* knob = stage == 0 ? &c.persistent : stage == 1 ? &c.waves_per_block : stage == 2 ? &c.lds_share
-                                                                                            : &c.xcd_chunk;
+      int* knob = stage == 0 ? &c.targets_per_lane : stage == 1 ? &c.persistent : stage == 2 ? &c.waves_per_block
+                  : stage == 3 ? &c.lds_share : &c.xcd_chunk;
       if (*knob == vals[v]) continue;
       *knob = vals[v];
       if ((rc = measure(c)) != BH_OK) break;
@@ -526,6 +534,7 @@ int bh_autotune(bh_tree* t, double theta, double eps, void* acc, void* pot, int 
   t->xcd_chunk = cur.xcd_chunk;
   t->lds_share64 = cur.lds_share;
   t->persistent = cur.persistent;
+  t->targets_per_lane = cur.targets_per_lane;
   (void)bh_set_timing(t, was_timing ? 1 : 0);
   if (rc != BH_OK) return rc;
   *best = cur;

@@ -39,18 +39,20 @@ struct alignas(64) Node {
 static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
 
 // The walk's copy of a node for one uniform theta: a cell carries its squared
-// opening size S = (l/theta + s)^2 in place of l, and the slot of s holds the
-// mass rounded to FP32.
+// opening size S = (l/theta + s)^2 (a leaf -1), and the mass also rounded to
+// FP32.  The fields one FP32 step reads (centre, S, M32, next, first, count,
+// meta) are the first 52 bytes, the FP32 mass beside the integers, so that
+// they arrive in one batch of scalar loads.
 struct alignas(64) WalkNode {
   double cx, cy, cz;
-  double M;
   double S;
   float M32;
-  int32_t pad;
   int32_t next;
   int32_t first;
   int32_t count;
   int32_t meta;
+  int32_t pad;
+  double M;
 };
 static_assert(sizeof(WalkNode) == 64, "WalkNode must be 64 bytes");
 

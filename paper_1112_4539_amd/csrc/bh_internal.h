@@ -84,6 +84,7 @@ struct WalkArgs {
   int persistent;              // 0: one wave per group; 1: waves pull groups from `queue`
   int32_t* queue;              // persistent: group counter, zeroed before the launch
   int grid;                    // persistent: workgroups launched
+  int targets_per_lane;        // 1 or 2: a wave walks 64 or 128 targets
 };
 
 enum WalkMode { kWalkForces = 0, kWalkStats = 1, kWalkDump = 2 };
@@ -91,7 +92,7 @@ enum WalkMode { kWalkForces = 0, kWalkStats = 1, kWalkDump = 2 };
 hipError_t launch_walk(bool f64, int mode, const WalkArgs& a, hipStream_t st);
 
 // Workgroups of the persistent walk resident on the current device at once.
-int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_per_block);
+int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_per_block, int targets_per_lane);
 
 // Walk copy of the nodes for one uniform theta: every record with its side l
 // replaced by S = (l/theta + s)^2 (Eq. (2) squared, the S_effective of Sec. 4.4)

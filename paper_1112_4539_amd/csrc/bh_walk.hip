@@ -96,11 +96,13 @@ __global__ __launch_bounds__(256) void k_mac_size(const Node* __restrict__ nodes
   const Node nd = nodes[c];
   const double u = fma(nd.l, inv_theta, nd.s);
   WalkNode w;
+  // a leaf is always "accepted" by the opening test (S = -1 < d^2): its
+  // particle is used unless it is the target itself
   w.cx = nd.cx;
   w.cy = nd.cy;
   w.cz = nd.cz;
   w.M = nd.M;
-  w.S = u * u;
+  w.S = (nd.meta & 1) ? -1.0 : u * u;
   w.M32 = (float)nd.M;
   w.pad = 0;
   w.next = nd.next;
@@ -128,10 +130,10 @@ struct StepNode;
 #define BH_CONST __attribute__((address_space(4)))
 template <typename Rec>
 __device__ __forceinline__ Rec const_load(const Rec* base, int c) {
-  const BH_CONST Rec* p = (const BH_CONST Rec*)(uintptr_t)base + c;
+  const BH_CONST Rec* p = (const BH_CONST Rec*)(uintptr_t)base + (uint32_t)c;
   Rec r;
   if constexpr (sizeof(Rec) == sizeof(WalkNode) && std::is_same<Rec, WalkNode>::value) {
-    r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.M = p->M; r.S = p->S; r.M32 = p->M32; r.pad = 0;
+    r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.S = p->S; r.M32 = p->M32; r.pad = 0; r.M = p->M;
   } else {
     r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.M = p->M; r.l = p->l; r.s = p->s;
   }
@@ -149,20 +151,15 @@ struct StepNode<true> {
   __device__ __forceinline__ Node load(int c) const { return const_load(base, c); }
 };
 
-// One walk: a cursor over the preorder node array shared by the wave, and the
-// per-lane state of the lane's target.
+// Per-target state of a walk.
 template <bool kF64>
-struct Cursor {
-  using R = typename std::conditional<kF64, double, float>::type;
+struct Target {
   typename std::conditional<kF64, AccF64, AccMixed>::type acc;
   double xi, yi, zi;   // target position (exactly widened)
   double inv_theta;
-  int i;               // Morton position of the target, -1 for an idle lane
+  int i;               // Morton position of the target, -1 for an idle slot
   int slot;            // position of the target in the walk order
-  int c;               // wave-uniform cursor
-  int skip;            // the lane is active at c iff skip <= c
-  int k, kend;         // position inside a leaf of several particles
-  int steps;
+  int skip;            // the target is active at c iff skip <= c
   int node0;           // preorder id of the root of the target's cluster (list words are relative)
   int idx0;            // caller index of the first particle of the target's cluster
   int32_t n_pp, n_pc;
@@ -171,18 +168,72 @@ struct Cursor {
   int64_t* list;
 };
 
-// One step of a walk at node `cur` (index cur_c = C.c).  kGuard: some target
-// of the wave has theta > 1, so a cell holding the target must be excluded
-// explicitly (for theta <= 1 such a cell fails the opening test by itself:
-// d <= (sqrt(3)/2) l + s < l/theta + s, a margin of 0.13 l that no rounding
-// reaches).
+// One walk: a cursor over the preorder node array shared by the wave, and the
+// kT targets of each lane (a wave walks 64 kT Morton-consecutive targets: lane
+// l holds targets l, 64 + l, ...).
+template <bool kF64, int kT>
+struct Cursor {
+  using R = typename std::conditional<kF64, double, float>::type;
+  Target<kF64> t[kT];
+  int c;               // wave-uniform cursor
+  int k, kend;         // position inside a leaf of several particles
+  int steps;
+};
+
+// A step at a leaf of several coincident-key particles (rare): one of its
+// particles per step, the cursor staying on the leaf until they are done.
+template <bool kF64, int kT, int kMode, bool kSoft, typename Rec>
+__device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& cur) {
+  using R4 = typename std::conditional<kF64, double4, float4>::type;
+  constexpr bool kStats = kMode != kWalkForces;
+  const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
+  const int c = C.c;
+  if (C.kend == 0) {
+    C.k = min(max(cur.first, 0), a.n);
+    C.kend = C.k + min(max(cur.count, 0), a.n - C.k);
+  }
+  const int kk = min(C.k, a.n - 1);
+  const R4 q = ps[kk];
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    Target<kF64>& T = C.t[t];
+    if (T.skip <= c && C.k < C.kend && kk != T.i) {
+      const double dx = (double)q.x - T.xi, dy = (double)q.y - T.yi, dz = (double)q.z - T.zi;
+      if constexpr (kF64) {
+        T.acc.term(dx, dy, dz, q.w, a.eps2);
+      } else {
+        T.acc.template term<kSoft>(dx, dy, dz, fma(dz, dz, fma(dy, dy, dx * dx)), q.w, a.eps2);
+      }
+      if constexpr (kStats) {
+        const uint64_t wd = (uint64_t)(a.perm[kk] - T.idx0) << 1;
+        ++T.n_pp;
+        T.h = (T.h ^ wd) * kFnvPrime;
+        if (kMode == kWalkDump && T.len < a.maxlen) T.list[T.len] = (int64_t)wd;
+        ++T.len;
+      }
+    }
+  }
+  if (++C.k < C.kend) {
+    C.c = c;
+  } else {
+    C.k = C.kend = 0;
+    C.c = c + 1;
+  }
+}
+
+// One step of a walk at node `cur` (index C.c).  A cell and a one-particle
+// leaf take the same path: the walk copy gives a leaf S = -1, so its opening
+// test always passes, and a node whose first particle is the target itself is
+// never used (for a cell that holds the target the test fails by itself when
+// theta <= 1: d <= (sqrt(3)/2) l + s < l/theta + s, a margin of 0.13 l that no
+// rounding reaches).  kGuard: some target of the wave has theta > 1, so a cell
+// holding the target is excluded by its particle range instead.
 //
-// Each step produces one source for the shared term: the cell (after the
-// opening test), the particle of a one-particle leaf, or one particle of a
-// leaf of coincident-key particles (the cursor stays on such a leaf until its
-// particles are done).  One term site keeps the sums in place.
-template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard, typename Rec>
-__device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64>& C, const Rec& rec) {
+// A target that uses the node adds its term and skips the node's subtree
+// (next(c); for a leaf that is c + 1 anyway); the cursor moves to c + 1 if an
+// active target did not use the node, else to next(c).
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, typename Rec>
+__device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& rec) {
   // The record was read from LDS by every lane; its integer fields steer the
   // wave's control flow, so take them as wave-uniform values.
   Rec cur = rec;
@@ -190,95 +241,78 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64>& C, co
   cur.first = uniform(rec.first);
   cur.count = uniform(rec.count);
   cur.meta = uniform(rec.meta);
-  using R = typename Cursor<kF64>::R;
-  using R4 = typename std::conditional<kF64, double4, float4>::type;
+  using R = typename Cursor<kF64, kT>::R;
   constexpr bool kStats = kMode != kWalkForces;
-  const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
   const int c = C.c;
-  const int i = C.i;
   if constexpr (kStats) ++C.steps;
   const int nnext = max(cur.next, c + 1);
-  const int kind = cur.meta & 3;  // 0 cell, 1 one-particle leaf, 3 several-particle leaf
-  const bool act = C.skip <= c;
-  const uint64_t m_act = ballot(act);
-  // Offset to the node's position (cell: centre of mass; one-particle leaf:
-  // its particle), formed in FP64.  For FP32 input the FP64 difference of the
-  // widened coordinates is exact, so its FP32 rounding equals a direct FP32
-  // subtraction; a cell's offset is rounded once.  Formed for every node so
-  // that the whole record is read at the top of the step.
-  double dx = cur.cx - C.xi, dy = cur.cy - C.yi, dz = cur.cz - C.zi;
-  // Opening test of Eq. (2) in FP64, also evaluated (and ignored) for leaves
-  // so that no field load is left for later in the step.
-  double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  double S;
-  if constexpr (kPlain) {
-    const double u = fma(cur.l, C.inv_theta, cur.s);
-    S = u * u;
-  } else {
-    S = cur.S;
-  }
-  bool pass = d2 > S;
-  if constexpr (kGuard) pass = pass && !((unsigned)(i - cur.first) < (unsigned)cur.count);
-  // (a ballot is convergent: it keeps the test, and the loads it needs, here)
-  const uint64_t m_pass = ballot(pass);
-  R tm;
-  bool use;
-  uint64_t m_use;
-  int cnext = nnext;
-  int src = cur.first;  // Morton position of a particle source
-  if (kind == 0) {
-    // Cell: a cell term for the lanes that accept it.
-    use = act && pass;
-    m_use = m_act & m_pass;
-    if (m_act & ~m_pass) cnext = c + 1;
-    if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
-  } else if (kind == 1) {
-    // One-particle leaf: a particle term unless the particle is i.
-    use = act && cur.first != i;
-    m_use = m_act & ballot(cur.first != i);
-    if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
-  } else {
-    // Leaf of coincident-key particles: one of its particles per step.
-    if (C.kend == 0) {
-      C.k = min(max(cur.first, 0), a.n);
-      C.kend = C.k + min(max(cur.count, 0), a.n - C.k);
-    }
-    const int kk = min(C.k, a.n - 1);
-    src = kk;
-    const R4 q = ps[kk];
-    use = act && C.k < C.kend && kk != i;
-    m_use = m_act & ballot(C.k < C.kend && kk != i);
-    // the step's source is this particle: its offset replaces the node's
-    dx = (double)q.x - C.xi;
-    dy = (double)q.y - C.yi;
-    dz = (double)q.z - C.zi;
-    d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    tm = q.w;
-    if (++C.k < C.kend) {
-      cnext = c;
+  bool use[kT];
+  uint64_t m_use = 0, m_open = 0;
+  double dx[kT], dy[kT], dz[kT], d2[kT];
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const Target<kF64>& T = C.t[t];
+    const bool act = T.skip <= c;
+    const uint64_t m_act = ballot(act);
+    // Offset to the node's position (cell: centre of mass; leaf: its
+    // particle), formed in FP64.  For FP32 input the FP64 difference of the
+    // widened coordinates is exact, so its FP32 rounding equals a direct FP32
+    // subtraction; a cell's offset is rounded once.
+    dx[t] = cur.cx - T.xi;
+    dy[t] = cur.cy - T.yi;
+    dz[t] = cur.cz - T.zi;
+    // Opening test of Eq. (2) in FP64.
+    d2[t] = fma(dz[t], dz[t], fma(dy[t], dy[t], dx[t] * dx[t]));
+    double S;
+    if constexpr (kPlain) {
+      const double u = fma(cur.l, T.inv_theta, cur.s);
+      S = (cur.meta & 1) ? -1.0 : u * u;
     } else {
-      C.k = C.kend = 0;
+      S = cur.S;
     }
+    bool pass = d2[t] > S;
+    if constexpr (kGuard)
+      pass = pass && (unsigned)(T.i - cur.first) >= (unsigned)cur.count;
+    else
+      pass = pass && T.i != cur.first;
+    // (a ballot is convergent: it keeps the test, and the loads it needs, here)
+    const uint64_t m_pass = ballot(pass);
+    use[t] = act && pass;
+    m_use |= m_act & m_pass;
+    m_open |= m_act & ~m_pass;
   }
+  // (the test above runs for every node, so that the whole record is read at
+  // the top of the step; a leaf of several particles then goes its own way)
+  if (cur.meta & 2) {
+    bucket_step<kF64, kT, kMode, kSoft>(a, C, cur);
+    return;
+  }
+  R tm;
+  if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
   if (m_use) {
-    if (use) {
-      if constexpr (kF64) {
-        C.acc.term(dx, dy, dz, tm, a.eps2);
-      } else {
-        C.acc.template term<kSoft>(dx, dy, dz, d2, tm, a.eps2);
-      }
-      if (kind == 0) C.skip = nnext;
-      if constexpr (kStats) {
-        const uint64_t wd = kind == 0 ? (((uint64_t)(c - C.node0) << 1) | 1ull)
-                                      : ((uint64_t)(a.perm[src] - C.idx0) << 1);
-        if (kind == 0) ++C.n_pc; else ++C.n_pp;
-        C.h = (C.h ^ wd) * kFnvPrime;
-        if (kMode == kWalkDump && C.len < a.maxlen) C.list[C.len] = (int64_t)wd;
-        ++C.len;
+    const bool cell = (cur.meta & 1) == 0;
+#pragma unroll
+    for (int t = 0; t < kT; ++t) {
+      Target<kF64>& T = C.t[t];
+      if (use[t]) {
+        if constexpr (kF64) {
+          T.acc.term(dx[t], dy[t], dz[t], tm, a.eps2);
+        } else {
+          T.acc.template term<kSoft>(dx[t], dy[t], dz[t], d2[t], tm, a.eps2);
+        }
+        T.skip = nnext;
+        if constexpr (kStats) {
+          const uint64_t wd = cell ? (((uint64_t)(c - T.node0) << 1) | 1ull)
+                                   : ((uint64_t)(a.perm[cur.first] - T.idx0) << 1);
+          if (cell) ++T.n_pc; else ++T.n_pp;
+          T.h = (T.h ^ wd) * kFnvPrime;
+          if (kMode == kWalkDump && T.len < a.maxlen) T.list[T.len] = (int64_t)wd;
+          ++T.len;
+        }
       }
     }
   }
-  C.c = cnext;
+  C.c = m_open ? c + 1 : nnext;
 }
 
 // Node records reach the walk through LDS.  The walk reads one record per
@@ -306,14 +340,14 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 // the node capacity, so a corrupted record can never send the cursor out of the
 // array, and every step moves the cursor forward or stays on a leaf for at most
 // its particle count.
-template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard>
-__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C,
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard>
+__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
                                                  int end) {
-  while (C.c < end) walk_step<kF64, kMode, kSoft, kPlain, kGuard>(a, C, wn.load(C.c));
+  while (C.c < end) walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, C, wn.load(C.c));
 }
 
-template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard>
-__device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C,
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard>
+__device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
                                               uint4 (*pf)[8], int end) {
   using Rec = decltype(wn.load(0));
   const int cap = 2 * a.n;
@@ -329,7 +363,7 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain
     const Rec rec = reinterpret_cast<const Rec*>(pf[buf])[slot];
     const int nnext = max(uniform(rec.next), c + 1);
     fetch_pair(wn.base, min(c + 1, cap - 1), min(nnext, cap - 1), lane, pf[buf ^ 1]);
-    walk_step<kF64, kMode, kSoft, kPlain, kGuard>(a, C, rec);
+    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, C, rec);
     if (C.c != c) {  // moved on (a leaf of several particles keeps the cursor)
       slot = C.c == c + 1 ? 0 : 1;
       buf ^= 1;
@@ -337,72 +371,84 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain
   }
 }
 
-// The clusters klo..khi of a wave, one subtree after the other; lanes of the
+// The clusters klo..khi of a wave, one subtree after the other; targets of the
 // other clusters stay idle (skip past the subtree).
-template <bool kF64, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kLds>
-__device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64>& C,
-                                              uint4 (*pf)[8], bool valid, int kc, int klo, int khi) {
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kLds>
+__device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
+                                              uint4 (*pf)[8], const int (&kc)[kT], int klo, int khi) {
   const int cap = 2 * a.n;
   for (int k = klo; k <= khi; ++k) {
     const int r0 = min(max(uniform(a.croot[k]), 0), cap);
     const int r1 = min(max(uniform(a.croot[k + 1]), r0), cap);
     C.c = r0;
     C.k = C.kend = 0;
-    C.skip = (valid && kc == k) ? r0 : 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < kT; ++t) C.t[t].skip = (C.t[t].i >= 0 && kc[t] == k) ? r0 : 0x7fffffff;
     if (r0 >= r1) continue;
     if constexpr (kLds)
-      walk_loop_lds<kF64, kMode, kSoft, kPlain, kGuard>(a, wn, C, pf, r1);
+      walk_loop_lds<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, wn, C, pf, r1);
     else
-      walk_loop_scalar<kF64, kMode, kSoft, kPlain, kGuard>(a, wn, C, r1);
+      walk_loop_scalar<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, wn, C, r1);
   }
 }
 
-// The walk of one group of 64 targets (one wavefront).
+// The walk of one group of 64 kT targets (one wavefront).
 // kSoft: eps > 0, so r^2 + eps^2 > 0 and the FP32 term needs no zero test.
 // kGroupTheta: theta per 64-particle Morton group instead of one uniform theta
 // (uniform theta walks the copy with S precomputed).
-template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kGroupTheta>
 __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (*pf)[8]) {
-  using R = typename Cursor<kF64>::R;
+  using R = typename Cursor<kF64, kT>::R;
   using R4 = typename std::conditional<kF64, double4, float4>::type;
   constexpr bool kStats = kMode != kWalkForces;
   const int lane = __lane_id();
   const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
 
-  Cursor<kF64> C;
-  C.slot = group * kWave + lane;
-  const bool valid = C.slot < a.n;
-  C.i = valid ? (a.order ? a.order[C.slot] : C.slot) : -1;
-  R4 me;
-  if (valid) {
-    me = ps[C.i];
-  } else {
-    me.x = me.y = me.z = me.w = (R)0;
-  }
-  C.xi = (double)me.x;
-  C.yi = (double)me.y;
-  C.zi = (double)me.z;
-  C.inv_theta = kGroupTheta ? 1.0 / (double)a.theta_group[valid ? (C.i >> 6) : 0] : a.inv_theta;
-  C.acc.init();
+  Cursor<kF64, kT> C;
   C.k = C.kend = 0;
   C.steps = 0;
-  C.n_pp = C.n_pc = 0;
-  C.h = kFnvOffset;
-  C.len = 0;
-  C.list = (kMode == kWalkDump && valid) ? a.lists + (int64_t)a.perm[C.i] * a.maxlen : nullptr;
-  const bool guard = ballot(valid && C.inv_theta < 1.0) != 0ull;
-  // Clusters of the wave's targets: a wave usually lies inside one cluster; one
-  // that straddles cluster edges walks each cluster's subtree in turn.
-  const int kc = valid ? min(max(a.scid[C.i], 0), a.n_seg - 1) : 0;
-  int klo = valid ? kc : 0x7fffffff, khi = valid ? kc : -1;
+  bool guard_l = false;
+  int kc[kT];
+  int klo = 0x7fffffff, khi = -1;
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    Target<kF64>& T = C.t[t];
+    T.slot = (group * kT + t) * kWave + lane;
+    const bool valid = T.slot < a.n;
+    T.i = valid ? (a.order ? a.order[T.slot] : T.slot) : -1;
+    R4 me;
+    if (valid) {
+      me = ps[T.i];
+    } else {
+      me.x = me.y = me.z = me.w = (R)0;
+    }
+    T.xi = (double)me.x;
+    T.yi = (double)me.y;
+    T.zi = (double)me.z;
+    T.inv_theta = kGroupTheta ? 1.0 / (double)a.theta_group[valid ? (T.i >> 6) : 0] : a.inv_theta;
+    T.acc.init();
+    T.n_pp = T.n_pc = 0;
+    T.h = kFnvOffset;
+    T.len = 0;
+    T.list = (kMode == kWalkDump && valid) ? a.lists + (int64_t)a.perm[T.i] * a.maxlen : nullptr;
+    guard_l = guard_l || (valid && T.inv_theta < 1.0);
+    // Clusters of the wave's targets: a wave usually lies inside one cluster;
+    // one that straddles cluster edges walks each cluster's subtree in turn.
+    kc[t] = valid ? min(max(a.scid[T.i], 0), a.n_seg - 1) : 0;
+    if (valid) {
+      klo = min(klo, kc[t]);
+      khi = max(khi, kc[t]);
+    }
+    T.node0 = valid ? a.croot[kc[t]] : 0;
+    T.idx0 = valid ? (int)a.seg_off[kc[t]] : 0;
+  }
+  const bool guard = ballot(guard_l) != 0ull;
   for (int o = 32; o > 0; o >>= 1) {
     klo = min(klo, __shfl_xor(klo, o, 64));
     khi = max(khi, __shfl_xor(khi, o, 64));
   }
   klo = uniform(klo);
   khi = uniform(khi);
-  C.node0 = valid ? a.croot[kc] : 0;
-  C.idx0 = valid ? (int)a.seg_off[kc] : 0;
   StepNode<kGroupTheta> wn;
   if constexpr (kGroupTheta) wn.base = a.nodes; else wn.base = a.wnodes;
   // Waves split between the two node paths (scalar cache / LDS copies) so
@@ -417,122 +463,130 @@ __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (
   // node array as unwritten and drops the scalar loads)
   if (lds_path) {
     if (guard)
-      walk_clusters<kF64, kMode, kSoft, kGroupTheta, true, true>(a, wn, C, pf, valid, kc, klo, khi);
+      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true>(a, wn, C, pf, kc, klo, khi);
     else
-      walk_clusters<kF64, kMode, kSoft, kGroupTheta, false, true>(a, wn, C, pf, valid, kc, klo, khi);
+      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true>(a, wn, C, pf, kc, klo, khi);
   } else {
     if (guard)
-      walk_clusters<kF64, kMode, kSoft, kGroupTheta, true, false>(a, wn, C, pf, valid, kc, klo, khi);
+      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false>(a, wn, C, pf, kc, klo, khi);
     else
-      walk_clusters<kF64, kMode, kSoft, kGroupTheta, false, false>(a, wn, C, pf, valid, kc, klo, khi);
+      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false>(a, wn, C, pf, kc, klo, khi);
   }
 
-  if (kStats && a.group_steps && lane == 0 && valid) a.group_steps[group] = C.steps;
-  if (!valid) return;
-  const int o = a.perm[C.i];
-  R* accp = reinterpret_cast<R*>(a.acc);
-  R* potp = reinterpret_cast<R*>(a.pot);
-  accp[3 * (int64_t)o] = (R)C.acc.ax;
-  accp[3 * (int64_t)o + 1] = (R)C.acc.ay;
-  accp[3 * (int64_t)o + 2] = (R)C.acc.az;
-  potp[o] = (R)C.acc.p;
-  if constexpr (kStats) {
-    a.counts[2 * (int64_t)o] = C.n_pp;
-    a.counts[2 * (int64_t)o + 1] = C.n_pc;
-    a.hash[o] = C.h;
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const Target<kF64>& T = C.t[t];
+    if (T.i < 0) continue;
+    if (kStats && a.group_steps && lane == 0) a.group_steps[T.slot >> 6] = C.steps;
+    const int o = a.perm[T.i];
+    R* accp = reinterpret_cast<R*>(a.acc);
+    R* potp = reinterpret_cast<R*>(a.pot);
+    accp[3 * (int64_t)o] = (R)T.acc.ax;
+    accp[3 * (int64_t)o + 1] = (R)T.acc.ay;
+    accp[3 * (int64_t)o + 2] = (R)T.acc.az;
+    potp[o] = (R)T.acc.p;
+    if constexpr (kStats) {
+      a.counts[2 * (int64_t)o] = T.n_pp;
+      a.counts[2 * (int64_t)o + 1] = T.n_pc;
+      a.hash[o] = T.h;
+    }
   }
 }
 
-// One wavefront per group; workgroups of waves_per_block waves.
-template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
+// One wavefront per group of 64 kT targets; workgroups of waves_per_block waves.
+template <bool kF64, int kT, int kMode, bool kSoft, bool kGroupTheta>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
   __shared__ uint4 pf_lds[4][2][8];  // per wave: two buffers of two 64-byte node records
   const int wv = threadIdx.x >> 6;
   const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_chunk);
   // (a wave past the last target has no valid lane and walks nothing)
-  walk_group<kF64, kMode, kSoft, kGroupTheta>(a, blk * a.waves_per_block + wv, pf_lds[wv]);
+  walk_group<kF64, kT, kMode, kSoft, kGroupTheta>(a, blk * a.waves_per_block + wv, pf_lds[wv]);
 }
 
 // Persistent form: a grid that fits on the chip at once; every wave takes the
 // next group from a device counter until none is left, so the load balances
 // itself and no workgroup waits for a dispatch slot.  Every wave leaves once
 // the counter passes the last group.
-template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kGroupTheta>
 __global__ __launch_bounds__(256) void k_walk_persistent(WalkArgs a) {
   __shared__ uint4 pf_lds[4][2][8];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int groups = (a.n + kWave - 1) / kWave;
+  const int groups = (a.n + kT * kWave - 1) / (kT * kWave);
   for (;;) {
     int g = 0;
     if (lane == 0) g = atomicAdd(a.queue, 1);
     g = __shfl(g, 0, 64);
     if (g >= groups) break;
-    walk_group<kF64, kMode, kSoft, kGroupTheta>(a, g, pf_lds[wv]);
+    walk_group<kF64, kT, kMode, kSoft, kGroupTheta>(a, g, pf_lds[wv]);
   }
 }
 
-template <bool kF64, int kMode, bool kSoft, bool kGroupTheta>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kGroupTheta>
 static hipError_t launch_t(const WalkArgs& a, hipStream_t st) {
-  const int groups = (a.n + kWave - 1) / kWave;
+  const int groups = (a.n + kT * kWave - 1) / (kT * kWave);
   const int wpb = a.waves_per_block;
   const int blocks = (groups + wpb - 1) / wpb;
   if (a.persistent) {
     hipError_t e = fill_i32(a.queue, 1, 0, st);
     if (e != hipSuccess) return e;
-    k_walk_persistent<kF64, kMode, kSoft, kGroupTheta><<<max(1, min(a.grid, blocks)), wpb * kWave, 0, st>>>(a);
+    k_walk_persistent<kF64, kT, kMode, kSoft, kGroupTheta><<<max(1, min(a.grid, blocks)), wpb * kWave, 0, st>>>(a);
   } else {
-    k_walk<kF64, kMode, kSoft, kGroupTheta><<<blocks, wpb * kWave, 0, st>>>(a);
+    k_walk<kF64, kT, kMode, kSoft, kGroupTheta><<<blocks, wpb * kWave, 0, st>>>(a);
   }
   return hipGetLastError();
 }
 
-template <bool kF64, int kMode>
+template <bool kF64, int kT, int kMode>
 static const void* persistent_fn(bool soft, bool group_theta) {
   if (soft)
-    return group_theta ? reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, true, true>)
-                       : reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, true, false>);
-  return group_theta ? reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, false, true>)
-                     : reinterpret_cast<const void*>(&k_walk_persistent<kF64, kMode, false, false>);
+    return group_theta ? reinterpret_cast<const void*>(&k_walk_persistent<kF64, kT, kMode, true, true>)
+                       : reinterpret_cast<const void*>(&k_walk_persistent<kF64, kT, kMode, true, false>);
+  return group_theta ? reinterpret_cast<const void*>(&k_walk_persistent<kF64, kT, kMode, false, true>)
+                     : reinterpret_cast<const void*>(&k_walk_persistent<kF64, kT, kMode, false, false>);
+}
+
+template <bool kF64, int kT>
+static const void* persistent_fn_mode(int mode, bool soft, bool group_theta) {
+  return mode == kWalkForces  ? persistent_fn<kF64, kT, kWalkForces>(soft, group_theta)
+         : mode == kWalkStats ? persistent_fn<kF64, kT, kWalkStats>(soft, group_theta)
+                              : persistent_fn<kF64, kT, kWalkDump>(soft, group_theta);
 }
 
 // Workgroups of the persistent walk that are resident on the chip at once (0 if
 // the runtime cannot tell).
-int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_per_block) {
+int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_per_block, int targets_per_lane) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* fn;
-  if (f64)
-    fn = mode == kWalkForces ? persistent_fn<true, kWalkForces>(soft, group_theta)
-       : mode == kWalkStats  ? persistent_fn<true, kWalkStats>(soft, group_theta)
-                             : persistent_fn<true, kWalkDump>(soft, group_theta);
-  else
-    fn = mode == kWalkForces ? persistent_fn<false, kWalkForces>(soft, group_theta)
-       : mode == kWalkStats  ? persistent_fn<false, kWalkStats>(soft, group_theta)
-                             : persistent_fn<false, kWalkDump>(soft, group_theta);
+  const bool two = targets_per_lane == 2;
+  const void* fn = f64 ? (two ? persistent_fn_mode<true, 2>(mode, soft, group_theta)
+                              : persistent_fn_mode<true, 1>(mode, soft, group_theta))
+                       : (two ? persistent_fn_mode<false, 2>(mode, soft, group_theta)
+                              : persistent_fn_mode<false, 1>(mode, soft, group_theta));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, waves_per_block * kWave, 0) != hipSuccess) return 0;
   return cus * per_cu;
 }
 
-template <bool kF64, int kMode>
+template <bool kF64, int kT, int kMode>
 static hipError_t launch_mode(const WalkArgs& a, hipStream_t st) {
   const bool soft = a.eps2 > 0.0;
   if (a.theta_group)
-    return soft ? launch_t<kF64, kMode, true, true>(a, st) : launch_t<kF64, kMode, false, true>(a, st);
-  return soft ? launch_t<kF64, kMode, true, false>(a, st) : launch_t<kF64, kMode, false, false>(a, st);
+    return soft ? launch_t<kF64, kT, kMode, true, true>(a, st) : launch_t<kF64, kT, kMode, false, true>(a, st);
+  return soft ? launch_t<kF64, kT, kMode, true, false>(a, st) : launch_t<kF64, kT, kMode, false, false>(a, st);
+}
+
+template <bool kF64, int kT>
+static hipError_t launch_prec(int mode, const WalkArgs& a, hipStream_t st) {
+  if (mode == kWalkForces) return launch_mode<kF64, kT, kWalkForces>(a, st);
+  if (mode == kWalkStats) return launch_mode<kF64, kT, kWalkStats>(a, st);
+  return launch_mode<kF64, kT, kWalkDump>(a, st);
 }
 
 hipError_t launch_walk(bool f64, int mode, const WalkArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  if (f64) {
-    if (mode == kWalkForces) return launch_mode<true, kWalkForces>(a, st);
-    if (mode == kWalkStats) return launch_mode<true, kWalkStats>(a, st);
-    return launch_mode<true, kWalkDump>(a, st);
-  }
-  if (mode == kWalkForces) return launch_mode<false, kWalkForces>(a, st);
-  if (mode == kWalkStats) return launch_mode<false, kWalkStats>(a, st);
-  return launch_mode<false, kWalkDump>(a, st);
+  if (a.targets_per_lane == 2) return f64 ? launch_prec<true, 2>(mode, a, st) : launch_prec<false, 2>(mode, a, st);
+  return f64 ? launch_prec<true, 1>(mode, a, st) : launch_prec<false, 1>(mode, a, st);
 }
 
 }  // namespace bh

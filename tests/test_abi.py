@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_argument_checks():
     import paper_1112_4539_amd as bh
     lib = bh.load()
-    assert lib.bh_version() == 1
+    assert lib.bh_version() == 2
     assert lib.bh_workspace_bytes(-1, 0) == -1
     assert lib.bh_workspace_bytes(1 << 31, 0) == -1
     assert lib.bh_workspace_bytes(10, 7) == -1
@@ -57,7 +57,7 @@ def test_host_side_argument_checks():
     assert b"workspace" in lib.bh_last_error()
     assert lib.bh_forces(None, 0.5, 0.01, None, None, None) == -1
     assert lib.bh_direct(None, None, 10, 0, None, 5, -1.0, None, None, None) == -1
-    assert lib.bh_set_walk_config(None, 4, 0, 0, 0, 0) == -1
+    assert lib.bh_set_walk_config(None, 4, 0, 0, 0, 0, 1) == -1
     out = ctypes.c_void_p()
     assert lib.bh_build_forest(None, None, None, 2, 10, 0, None, 0, None, ctypes.byref(out)) == -1
     assert lib.bh_forest_workspace_bytes(10, 0, 0) == -1

@@ -60,12 +60,13 @@ def _small_forest():
     return pos, mass, off
 
 
-def _forest_vs_alone(bh, pos, mass, off, prec, theta, eps, clusters=None, check_nodes=True):
+def _forest_vs_alone(bh, pos, mass, off, prec, theta, eps, clusters=None, check_nodes=True, tpl=1):
     dt = _dt(prec)
     gp = torch.tensor(pos, dtype=dt, device="cuda")
     gm = torch.tensor(mass, dtype=dt, device="cuda")
     go = torch.tensor(off, dtype=torch.int64, device="cuda")
     F = bh.build_forest(gp, gm, go)
+    F.set_walk_config(targets_per_lane=tpl)
     F.check()
     st = F.walk_stats(theta, eps)
     a_f, p_f = F.forces(theta, eps)
@@ -96,11 +97,11 @@ def _forest_vs_alone(bh, pos, mass, off, prec, theta, eps, clusters=None, check_
     return F, st
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_forest_equals_clusters_alone(bh, prec):
-    say(f"[forest] small awkward clusters {prec}")
+@pytest.mark.parametrize("prec,tpl", [("fp32", 1), ("fp64", 1), ("fp32", 2)])
+def test_forest_equals_clusters_alone(bh, prec, tpl):
+    say(f"[forest] small awkward clusters {prec}, {tpl} targets per lane in the forest")
     pos, mass, off = _small_forest()
-    _forest_vs_alone(bh, pos, mass, off, prec, 0.6, 0.01)
+    _forest_vs_alone(bh, pos, mass, off, prec, 0.6, 0.01, tpl=tpl)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -166,9 +167,10 @@ def test_forest_full_size(bh):
         assert force_err(acc, w["acc"], w["amag"]).max() <= F32_TOL
     # persistent walk of the whole forest: same bits
     a0, p0 = st["acc"], st["pot"]
-    F.set_walk_config(4, 0, 0, 16, 1)
-    a1, p1 = F.forces(0.5, 0.01)
-    assert torch.equal(a1, a0) and torch.equal(p1, p0)
+    for tpl in (1, 2):
+        F.set_walk_config(4, 0, 0, 16, 1, tpl)
+        a1, p1 = F.forces(0.5, 0.01)
+        assert torch.equal(a1, a0) and torch.equal(p1, p0)
 
 
 @pytest.mark.parametrize("forest", [False, True])
@@ -183,7 +185,7 @@ def test_graph_replays_match_eager(bh, forest):
     gm = torch.tensor(mass, dtype=torch.float32, device="cuda")
     go = None if off is None else torch.tensor(off, device="cuda")
     T = bh.Tree(gp, gm, offsets=go)
-    T.set_walk_config(2, 0, 0, 16, 1)
+    T.set_walk_config(2, 0, 0, 16, 1, 2)
     acc = torch.zeros((len(pos), 3), dtype=torch.float32, device="cuda")
     pot = torch.zeros((len(pos),), dtype=torch.float32, device="cuda")
     G = T.graph(0.5, 0.01, acc, pot)
@@ -210,7 +212,7 @@ def test_autotune_keeps_results(bh):
     a_ref, p_ref = ref[0].clone(), ref[1].clone()
     best, tried = T.autotune(0.5, 1e-4, reps=1)
     say(f"  best {best}  ({len(tried)} tried)")
-    assert len(tried) >= 7   # 1 + 1 + 2 + 3, plus 2 more when the block-order walk wins
+    assert len(tried) >= 8   # 1 + 1 + 1 + 2 + 3, plus 2 more when the block-order walk wins
     assert best["ms"] == min(t["ms"] for t in tried)
     a, p = T.forces(0.5, 1e-4)
     assert torch.equal(a, a_ref) and torch.equal(p, p_ref)

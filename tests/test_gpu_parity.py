@@ -88,9 +88,10 @@ def test_tree_bitexact_workloads(bh, which, prec):
     _compare_trees(bh, pos, mass, prec)
 
 
-def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta_group=None):
+def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta_group=None, tpl=1):
     gp, gm = _gpu(pos, mass, prec)
     T = bh.Tree(gp, gm)
+    T.set_walk_config(targets_per_lane=tpl)
     tg_t = None if theta_group is None else torch.tensor(theta_group, dtype=torch.float32, device="cuda")
     out = T.walk_stats(theta, eps, theta_group=tg_t, maxlen=maxlen)
     acc_f, pot_f = T.forces(theta, eps, theta_group=tg_t)
@@ -117,33 +118,36 @@ def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta
     return acc, pot, w
 
 
-def test_lists_and_forces_plummer4k_fp64(bh):
-    say("[walk] plummer4k fp64 theta=0.5 full list dump")
+@pytest.mark.parametrize("tpl", [1, 2])
+def test_lists_and_forces_plummer4k_fp64(bh, tpl):
+    say(f"[walk] plummer4k fp64 theta=0.5 full list dump, {tpl} targets per lane")
     pos, mass = inputs.plummer(4096, 0)
-    acc, pot, w = _walk_compare(bh, pos, mass, "fp64", 0.5, 0.01, maxlen=4096)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp64", 0.5, 0.01, maxlen=4096, tpl=tpl)
     e = force_err(acc, w["acc"], w["amag"])
     say(f"  max err {e.max():.3e}  bit-exact share {np.mean(np.all(acc == w['acc'], axis=1)):.4f}")
     assert e.max() <= F64_TOL
     assert pot_err(pot, w["pot"]).max() <= F64_TOL
 
 
+@pytest.mark.parametrize("tpl", [1, 2])
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.75])
-def test_lists_and_forces_plummer4k_fp32(bh, theta):
-    say(f"[walk] plummer4k fp32 theta={theta} full list dump")
+def test_lists_and_forces_plummer4k_fp32(bh, theta, tpl):
+    say(f"[walk] plummer4k fp32 theta={theta} full list dump, {tpl} targets per lane")
     pos, mass = inputs.plummer(4096, 0)
-    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, 0.01, maxlen=4096)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, 0.01, maxlen=4096, tpl=tpl)
     e = force_err(acc, w["acc"], w["amag"])
     say(f"  max err {e.max():.3e} p99 {np.quantile(e, 0.99):.3e}")
     assert e.max() <= F32_TOL
     assert pot_err(pot, w["pot"]).max() <= F32_TOL
 
 
-def test_theta_per_group(bh):
-    say("[walk] per-group theta, clumpy 50k fp32")
+@pytest.mark.parametrize("tpl", [1, 2])
+def test_theta_per_group(bh, tpl):
+    say(f"[walk] per-group theta, clumpy 50k fp32, {tpl} targets per lane")
     pos, mass = inputs.clumpy(50_000, 31)
     g = (len(pos) + 63) // 64
     tg = np.random.default_rng(3).uniform(0.2, 1.0, g).astype(np.float32)
-    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.5, 1e-4, theta_group=tg)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.5, 1e-4, theta_group=tg, tpl=tpl)
     e = force_err(acc, w["acc"], w["amag"])
     say(f"  max err {e.max():.3e}")
     assert e.max() <= F32_TOL
@@ -199,11 +203,13 @@ def test_launch_shapes_and_target_order_bitexact(bh):
             for order in (0, 1):
                 for share in (0, 24, 64):
                     for pers in (0, 1):
-                        if pers and chunk:
-                            continue  # the block remap does not apply to the persistent walk
-                        T.set_walk_config(wpb, chunk, order, share, pers)
-                        a, p = T.forces(0.5, 1e-4)
-                        assert torch.equal(a, ref[0]) and torch.equal(p, ref[1]), (wpb, chunk, order, share, pers)
+                        for tpl in (1, 2):
+                            if pers and chunk:
+                                continue  # the block remap does not apply to the persistent walk
+                            T.set_walk_config(wpb, chunk, order, share, pers, tpl)
+                            a, p = T.forces(0.5, 1e-4)
+                            assert torch.equal(a, ref[0]) and torch.equal(p, ref[1]), (wpb, chunk, order, share,
+                                                                                       pers, tpl)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -246,13 +252,13 @@ def test_edge_cases(bh, prec):
         T.check()
 
 
-@pytest.mark.parametrize("name,theta", [("plummer1m", 0.3), ("plummer1m", 0.5), ("plummer1m", 0.75),
-                                        ("clumpy4m", 0.5)])
-def test_full_size_sampled(bh, name, theta):
-    say(f"[full] {name} theta={theta} (sampled targets)")
+@pytest.mark.parametrize("name,theta,tpl", [("plummer1m", 0.3, 1), ("plummer1m", 0.5, 1), ("plummer1m", 0.75, 1),
+                                            ("clumpy4m", 0.5, 1), ("clumpy4m", 0.35, 2)])
+def test_full_size_sampled(bh, name, theta, tpl):
+    say(f"[full] {name} theta={theta} (sampled targets), {tpl} targets per lane")
     pos, mass, spec = inputs.make(name)
     tg = inputs.sample_targets(len(pos), 2048, spec["seed"] + 100)
-    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, spec["eps"], targets=tg)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, spec["eps"], targets=tg, tpl=tpl)
     e = force_err(acc, w["acc"], w["amag"])
     say(f"  max err {e.max():.3e}  p99 {np.quantile(e, 0.99):.3e}  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
     assert e.max() <= F32_TOL
