@@ -247,7 +247,7 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
   if constexpr (kStats) ++C.steps;
   const int nnext = max(cur.next, c + 1);
   bool use[kT];
-  uint64_t m_use = 0, m_open = 0;
+  uint64_t m_open = 0;
   double dx[kT], dy[kT], dz[kT], d2[kT];
 #pragma unroll
   for (int t = 0; t < kT; ++t) {
@@ -270,26 +270,22 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
     } else {
       S = cur.S;
     }
-    bool pass = d2[t] > S;
-    if constexpr (kGuard)
-      pass = pass && (unsigned)(T.i - cur.first) >= (unsigned)cur.count;
-    else
-      pass = pass && T.i != cur.first;
+    // the opening test and the self test, each ballotted on its own so that
+    // both stay single compares writing a lane mask
+    const bool pd = d2[t] > S;
+    const bool ns = kGuard ? (unsigned)(T.i - cur.first) >= (unsigned)cur.count : T.i != cur.first;
     // (a ballot is convergent: it keeps the test, and the loads it needs, here)
-    const uint64_t m_pass = ballot(pass);
-    use[t] = act && pass;
-    m_use |= m_act & m_pass;
+    const uint64_t m_pass = ballot(pd) & ballot(ns);
+    use[t] = act && pd && ns;
     m_open |= m_act & ~m_pass;
   }
   // (the test above runs for every node, so that the whole record is read at
   // the top of the step; a leaf of several particles then goes its own way)
   if (cur.meta & 2) {
     bucket_step<kF64, kT, kMode, kSoft>(a, C, cur);
-    return;
-  }
-  R tm;
-  if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
-  if (m_use) {
+  } else {
+    R tm;
+    if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
     const bool cell = (cur.meta & 1) == 0;
 #pragma unroll
     for (int t = 0; t < kT; ++t) {
@@ -311,8 +307,8 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
         }
       }
     }
+    C.c = m_open ? c + 1 : nnext;
   }
-  C.c = m_open ? c + 1 : nnext;
 }
 
 // Node records reach the walk through LDS.  The walk reads one record per
