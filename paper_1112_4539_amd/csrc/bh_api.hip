@@ -176,6 +176,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   }
   bh::WalkArgs a{};
   a.nodes = t->w.nodes;
+  a.cnt = t->w.counts;
   a.wnodes = t->w.wnodes;
   a.ps = t->w.ps;
   a.perm = t->w.idx_a;

@@ -59,6 +59,7 @@ hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // positions; null = Morton order itself).
 struct WalkArgs {
   const Node* nodes;
+  const Counts* cnt;           // the build's counters (leaf count)
   const void* ps;              // float4 / double4 particles in Morton order
   const int32_t* perm;         // Morton position -> caller index
   const int32_t* order;        // optional target order (Morton positions), may be null

@@ -232,7 +232,7 @@ __device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>&
 // A target that uses the node adds its term and skips the node's subtree
 // (next(c); for a leaf that is c + 1 anyway); the cursor moves to c + 1 if an
 // active target did not use the node, else to next(c).
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, typename Rec>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, typename Rec>
 __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& rec) {
   // The record was read from LDS by every lane; its integer fields steer the
   // wave's control flow, so take them as wave-uniform values.
@@ -246,6 +246,13 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
   const int c = C.c;
   if constexpr (kStats) ++C.steps;
   const int nnext = max(cur.next, c + 1);
+  if constexpr (!kF64 && !kPlain) {
+    // Keep the FP32 mass in the step's first batch of scalar loads: it is used
+    // only by the term, and a load left to the term's branch would cost the
+    // step a second memory round trip.  (An empty statement that takes the
+    // value in a scalar register; it emits no instruction.)
+    asm volatile("" ::"s"(cur.M32));
+  }
   bool use[kT];
   uint64_t m_open = 0;
   double dx[kT], dy[kT], dz[kT], d2[kT];
@@ -270,18 +277,21 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
     } else {
       S = cur.S;
     }
-    // the opening test and the self test, each ballotted on its own so that
-    // both stay single compares writing a lane mask
     const bool pd = d2[t] > S;
     const bool ns = kGuard ? (unsigned)(T.i - cur.first) >= (unsigned)cur.count : T.i != cur.first;
-    // (a ballot is convergent: it keeps the test, and the loads it needs, here)
-    const uint64_t m_pass = ballot(pd) & ballot(ns);
     use[t] = act && pd && ns;
-    m_open |= m_act & ~m_pass;
+    // the same tests as lane masks, straight from the compares (ordered >,
+    // unsigned >= / !=) -- a ballot of the combined flag would first turn it
+    // into a number
+    const uint64_t m_pd = __builtin_amdgcn_fcmp(d2[t], S, 2);
+    const uint64_t m_ns = kGuard ? __builtin_amdgcn_uicmp((unsigned)(T.i - cur.first), (unsigned)cur.count, 35)
+                                 : __builtin_amdgcn_uicmp((unsigned)T.i, (unsigned)cur.first, 33);
+    m_open |= m_act & ~(m_pd & m_ns);
   }
   // (the test above runs for every node, so that the whole record is read at
-  // the top of the step; a leaf of several particles then goes its own way)
-  if (cur.meta & 2) {
+  // the top of the step; a leaf of several particles then goes its own way --
+  // kBucket: the tree has such leaves, known per walk from the build's counts)
+  if (kBucket && (cur.meta & 2)) {
     bucket_step<kF64, kT, kMode, kSoft>(a, C, cur);
   } else {
     R tm;
@@ -336,13 +346,13 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 // the node capacity, so a corrupted record can never send the cursor out of the
 // array, and every step moves the cursor forward or stays on a leaf for at most
 // its particle count.
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
 __device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
                                                  int end) {
-  while (C.c < end) walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, C, wn.load(C.c));
+  while (C.c < end) walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, wn.load(C.c));
 }
 
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
 __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
                                               uint4 (*pf)[8], int end) {
   using Rec = decltype(wn.load(0));
@@ -359,7 +369,7 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain
     const Rec rec = reinterpret_cast<const Rec*>(pf[buf])[slot];
     const int nnext = max(uniform(rec.next), c + 1);
     fetch_pair(wn.base, min(c + 1, cap - 1), min(nnext, cap - 1), lane, pf[buf ^ 1]);
-    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, C, rec);
+    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, rec);
     if (C.c != c) {  // moved on (a leaf of several particles keeps the cursor)
       slot = C.c == c + 1 ? 0 : 1;
       buf ^= 1;
@@ -369,7 +379,7 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain
 
 // The clusters klo..khi of a wave, one subtree after the other; targets of the
 // other clusters stay idle (skip past the subtree).
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kLds>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, bool kLds>
 __device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
                                               uint4 (*pf)[8], const int (&kc)[kT], int klo, int khi) {
   const int cap = 2 * a.n;
@@ -382,9 +392,9 @@ __device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kPlain
     for (int t = 0; t < kT; ++t) C.t[t].skip = (C.t[t].i >= 0 && kc[t] == k) ? r0 : 0x7fffffff;
     if (r0 >= r1) continue;
     if constexpr (kLds)
-      walk_loop_lds<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, wn, C, pf, r1);
+      walk_loop_lds<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, wn, C, pf, r1);
     else
-      walk_loop_scalar<kF64, kT, kMode, kSoft, kPlain, kGuard>(a, wn, C, r1);
+      walk_loop_scalar<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, wn, C, r1);
   }
 }
 
@@ -457,16 +467,34 @@ __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (
   // (one cluster loop per path and guard: the LDS path's copies must not share
   // a loop with the scalar path's loads, or the compiler stops treating the
   // node array as unwritten and drops the scalar loads)
+  // Leaves of several coincident-key particles exist iff some keys repeat
+  // (fewer leaves than particles); without them the step needs no branch for
+  // them.
+  const bool buckets = uniform(a.cnt->n_unique < a.n ? 1 : 0) != 0;
   if (lds_path) {
-    if (guard)
-      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true>(a, wn, C, pf, kc, klo, khi);
-    else
-      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true>(a, wn, C, pf, kc, klo, khi);
+    if (buckets) {
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true, true>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true, true>(a, wn, C, pf, kc, klo, khi);
+    } else {
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false, true>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false, true>(a, wn, C, pf, kc, klo, khi);
+    }
   } else {
-    if (guard)
-      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false>(a, wn, C, pf, kc, klo, khi);
-    else
-      walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false>(a, wn, C, pf, kc, klo, khi);
+    if (buckets) {
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true, false>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true, false>(a, wn, C, pf, kc, klo, khi);
+    } else {
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false, false>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false, false>(a, wn, C, pf, kc, klo, khi);
+    }
   }
 
 #pragma unroll
