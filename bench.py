@@ -155,10 +155,10 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=262144)
-    ap.add_argument("--waves-per-block", type=int, default=4)
+    ap.add_argument("--waves-per-block", type=int, default=1)
     ap.add_argument("--xcd-chunk", type=int, default=0)
     ap.add_argument("--target-order", type=int, default=0)
-    ap.add_argument("--lds-share", type=int, default=16)
+    ap.add_argument("--lds-share", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--targets-per-lane", type=int, default=1)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -295,7 +295,7 @@ def main():
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(args.workload, args.theta),
-            "kernel": "bh::k_walk<false,0>", "flops_per_unit": FLOPS_PER_INTERACTION,
+            "kernel": "bh::k_walk<false, 1, 0, true, false>", "flops_per_unit": FLOPS_PER_INTERACTION,
             "units_per_launch": inter,
         },
         "cpu_baseline": None,

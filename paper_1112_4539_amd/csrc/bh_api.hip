@@ -25,10 +25,10 @@ struct bh_tree {
   bh::BuildWs w{};
   int32_t* rank = nullptr;  // caller index -> Morton position
   int32_t* queue = nullptr; // group counter of the persistent walk
-  int waves_per_block = 4;
+  int waves_per_block = 1;
   int xcd_chunk = 0;
   int target_order = 0;
-  int lds_share64 = 16;
+  int lds_share64 = 0;
   int persistent = 0;
   int targets_per_lane = 1;
   bool timing = false;
