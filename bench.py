@@ -144,6 +144,144 @@ def forest_bench(args, bh, inputs):
     print(json.dumps(line), flush=True)
 
 
+def sweep_bench(args, bh, inputs):
+    """Plummer N=1,048,576 (seed 1, eps 0.005): per theta in {0.3, 0.5, 0.75}, the RMS and mean
+    relative force error against the FP64 direct sum on 65,536 sampled targets, interactions, and
+    the walk time with targets in Morton order and in the input (random) order; the FP64 walk
+    beside it as the accuracy reference of the FP32 arithmetic."""
+    pos, mass, spec = inputs.make("plummer1m")
+    eps = spec["eps"]
+    n = len(pos)
+    dev = torch.device("cuda:0")
+    g32 = (torch.tensor(pos.astype(np.float32), device=dev), torch.tensor(mass.astype(np.float32), device=dev))
+    g64 = (g32[0].double(), g32[1].double())
+    tg = torch.tensor(inputs.sample_targets(n, args.samples, spec["seed"]), device=dev)
+    a_ref, _ = bh.direct(g64[0], g64[1], eps, tg)
+    T32 = bh.Tree(*g32)
+    T64 = bh.Tree(*g64)
+
+    def walk_ms(T, theta, order, reps):
+        T.set_walk_config(target_order=order)
+        T.set_timing(True)
+        ms = []
+        for _ in range(reps):
+            T.forces(theta, eps)
+            ms.append(T.walk_time_ms())
+        T.set_timing(False)
+        T.set_walk_config(target_order=0)
+        return min(ms)
+
+    rows = []
+    for theta in spec["thetas"]:
+        st = T32.walk_stats(theta, eps)
+        inter = int(st["counts"].to(torch.int64).sum().item())
+        steps = int(st["group_steps"].to(torch.int64).sum().item())
+        d = (st["acc"][tg].double() - a_ref).norm(dim=1) / a_ref.norm(dim=1)
+        a64, _ = T64.forces(theta, eps)
+        d64 = (a64[tg] - a_ref).norm(dim=1) / a_ref.norm(dim=1)
+        d3264 = (st["acc"][tg].double() - a64[tg]).norm(dim=1) / a64[tg].norm(dim=1)
+        ms_m = walk_ms(T32, theta, 0, max(3, args.steps))
+        ms_r = walk_ms(T32, theta, 1, 2)
+        ms_64 = walk_ms(T64, theta, 0, 3)
+        row = dict(theta=theta, interactions=inter, mean_list=inter / n, lane_efficiency=inter / (64.0 * steps),
+                   rms_rel_err=float(torch.sqrt(torch.mean(d * d))), mean_rel_err=float(d.mean()),
+                   rms_rel_err_fp64_walk=float(torch.sqrt(torch.mean(d64 * d64))),
+                   max_rel_diff_fp32_vs_fp64_walk=float(d3264.max()),
+                   walk_ms_morton=ms_m, walk_ms_random_order=ms_r, random_over_morton=ms_r / ms_m,
+                   walk_ms_fp64=ms_64, interactions_per_s=inter / (ms_m * 1e-3))
+        log(f"[bench] theta={theta}: {json.dumps(row)}")
+        rows.append(row)
+    line = {"metric": "per-theta force error and localized-ordering effect, Plummer N=1M",
+            "value": rows[1]["interactions_per_s"], "unit": "interactions/s (theta 0.5, Morton order)",
+            "n_gpus": 1, "steps": args.steps, "warmup": 0, "ms_per_step": rows[1]["walk_ms_morton"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"Plummer sphere N={n} (a=1, truncated at 10a), seed {spec['seed']}, eps={eps}, FP32",
+                       "accuracy_targets": args.samples, "thetas": rows}}
+    print(json.dumps(line), flush=True)
+
+
+def learned_bench(args, bh, inputs):
+    """Learned per-group opening parameter against fixed theta at equal accuracy (RMS relative
+    force error 1e-3 against the FP64 direct sum on 65,536 sampled targets), on the clumpy field
+    N=8,388,608 (seed 4, eps 1e-4).  The network is trained on the GPU on 64 snapshots of
+    262,144 particles (seeds 100-163, Plummer and clumpy alternately); its shrink exponent is
+    picked on a held-out snapshot (seed 164).  Reported: interactions and walk time of the FP32
+    fixed-theta walk, the FP32 learned-theta walk, and the FP64 fixed-theta walk."""
+    from paper_1112_4539_amd import learn
+    t0 = time.perf_counter()
+    X, L = learn.build_dataset(range(100, 164), log=log)
+    t1 = time.perf_counter()
+    net, hist = learn.train(X, L, epochs=60, log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"[bench] labels {t1 - t0:.1f} s, training {t2 - t1:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    target = learn.TARGET
+
+    def evaluate(pos, mass, eps, n_targets, seed, betas, with_fp64):
+        dev = torch.device("cuda:0")
+        g32 = (torch.tensor(pos.astype(np.float32), device=dev), torch.tensor(mass.astype(np.float32), device=dev))
+        n = len(pos)
+        tg = torch.tensor(inputs.sample_targets(n, n_targets, seed), device=dev)
+        a_ref, _ = bh.direct(g32[0].double(), g32[1].double(), eps, tg)
+        T = bh.Tree(*g32)
+        raw = net.infer(T.features(), alpha=1.0, fallback=0.5)
+
+        def run(T, theta=None, tgrp=None, reps=3):
+            st = T.walk_stats(theta if theta else 0.5, eps, theta_group=tgrp)
+            inter = int(st["counts"].to(torch.int64).sum().item())
+            T.set_timing(True)
+            ms = []
+            for _ in range(reps):
+                T.forces(theta if theta else 0.5, eps, theta_group=tgrp)
+                ms.append(T.walk_time_ms())
+            T.set_timing(False)
+            return inter, min(ms)
+
+        def rms_fixed(T):
+            return lambda th: learn.rms_error(T.forces(th, eps)[0], a_ref, tg)
+
+        thf, ef = learn.bisect(rms_fixed(T), 0.1, 1.1, target)
+        i_f, ms_f = run(T, theta=thf)
+        out = {"fixed_fp32": dict(theta=thf, rms=ef, interactions=i_f, walk_ms=ms_f)}
+        for beta in betas:
+            def rms_l(alpha, beta=beta):
+                a, _ = T.forces(0.5, eps, theta_group=learn.scaled_theta(raw, alpha, beta))
+                return learn.rms_error(a, a_ref, tg)
+            al, el = learn.bisect(rms_l, 0.05, 4.0, target)
+            tgrp = learn.scaled_theta(raw, al, beta)
+            i_l, ms_l = run(T, tgrp=tgrp)
+            out[f"learned_beta{beta}"] = dict(alpha=al, beta=beta, rms=el, interactions=i_l, walk_ms=ms_l,
+                                              theta_mean=float(tgrp.mean()), interactions_vs_fixed=i_l / i_f,
+                                              walk_ms_vs_fixed=ms_l / ms_f)
+        if with_fp64:
+            T64 = bh.Tree(g32[0].double(), g32[1].double())
+            th64, e64 = learn.bisect(lambda th: learn.rms_error(T64.forces(th, eps)[0], a_ref, tg), 0.1, 1.1, target)
+            i64, ms64 = run(T64, theta=th64)
+            out["fixed_fp64"] = dict(theta=th64, rms=e64, interactions=i64, walk_ms=ms64)
+        return out
+
+    pos, mass, eps = learn.training_snapshot(164)
+    held = evaluate(pos, mass, eps, 65536, 164, (1.0, 0.8, 0.6, 0.4), False)
+    beta = min((v["interactions"], v["beta"]) for k, v in held.items() if k.startswith("learned"))[1]
+    log(f"[bench] held-out snapshot: {json.dumps(held)}; shrink exponent {beta}")
+    pos, mass, spec = inputs.make("clumpy8m")
+    res = evaluate(pos, mass, spec["eps"], args.samples, spec["seed"], (beta,), True)
+    log(f"[bench] clumpy 8M: {json.dumps(res)}")
+    n = len(pos)
+    lr = res[f"learned_beta{beta}"]
+    line = {"metric": "forces/s at RMS rel force err 1e-3, learned per-group theta (clumpy N=8M)",
+            "value": n / (lr["walk_ms"] * 1e-3), "unit": "forces/s (walk)", "n_gpus": 1, "steps": 3,
+            "warmup": 0, "ms_per_step": lr["walk_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, eps={spec['eps']}; trained on 64 "
+                                   f"snapshots N=262144 (seeds 100-163)",
+                       "train_rows": int(L.shape[0]), "train_loss": [hist[0], hist[-1]],
+                       "label_s": t1 - t0, "train_s": t2 - t1, "shrink_exponent": beta, "heldout": held,
+                       "eval": res,
+                       "forces_per_s": {k: n / (v["walk_ms"] * 1e-3) for k, v in res.items()}}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +312,10 @@ def main():
 
     if args.workload == "clusters512":
         return forest_bench(args, bh, inputs)
+    if args.workload == "plummer1m":
+        return sweep_bench(args, bh, inputs)
+    if args.workload == "learned":
+        return learned_bench(args, bh, inputs)
 
     if args.copy_calib > 0:
         # a plain copy of known size: reads and writes exactly MIB MiB each

@@ -150,6 +150,13 @@ def train(X, labels, epochs=40, batch=4096, lr=3e-3, lr_end=3e-4, seed=0, log=No
     return net, history
 
 
+def scaled_theta(raw, alpha, beta, cap=1.15):
+    """theta_g = min(alpha raw_g^beta, cap): the network's theta with one global scale alpha and a
+    shrink exponent beta <= 1 (beta < 1 pulls the per-group values toward their geometric mean,
+    which pays when the predictions are noisy)."""
+    return torch.clamp(alpha * raw.double() ** beta, max=cap).float().contiguous()
+
+
 def rms_error(acc, a_ref, targets):
     """RMS of |a - a_ref| / |a_ref| over the sampled targets (a_ref float64 [len(targets), 3])."""
     d = (acc[targets].double() - a_ref).norm(dim=1) / a_ref.norm(dim=1)
