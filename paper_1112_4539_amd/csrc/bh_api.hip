@@ -173,11 +173,16 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   if (!theta_group) {
     hipError_t e = bh::launch_mac_size(t->w.nodes, t->w.counts, (int)(2 * t->n), 1.0 / theta, t->w.wnodes, st);
     if (e != hipSuccess) return hip_fail(e, "launching the opening-size pass");
+  } else if (t->prec == BH_FP32) {
+    hipError_t e = bh::launch_theta_copy(t->w.nodes, t->w.counts, (int)(2 * t->n),
+                                         reinterpret_cast<bh::ThetaNode*>(t->w.wnodes), st);
+    if (e != hipSuccess) return hip_fail(e, "launching the per-group walk copy");
   }
   bh::WalkArgs a{};
   a.nodes = t->w.nodes;
   a.cnt = t->w.counts;
   a.wnodes = t->w.wnodes;
+  a.tnodes = reinterpret_cast<const bh::ThetaNode*>(t->w.wnodes);
   a.ps = t->w.ps;
   a.perm = t->w.idx_a;
   a.order = t->target_order == 1 ? t->rank : nullptr;

@@ -56,6 +56,23 @@ struct alignas(64) WalkNode {
 };
 static_assert(sizeof(WalkNode) == 64, "WalkNode must be 64 bytes");
 
+// The walk's copy of a node for per-group theta (FP32 walks): the opening size
+// is formed per step from l and s, S = (l/theta + s)^2; a leaf carries l = s =
+// 0, so S = 0 < d^2 for every particle but the target itself.  The fields of a
+// step are the first 56 bytes.
+struct alignas(64) ThetaNode {
+  double cx, cy, cz;
+  double l;
+  float M32;
+  int32_t next;
+  int32_t first;
+  int32_t count;
+  double s;
+  int32_t meta;
+  int32_t pad;
+};
+static_assert(sizeof(ThetaNode) == 64, "ThetaNode must be 64 bytes");
+
 // Root cube and Morton quantisation, computed on the device by the bbox pass.
 struct Cube {
   double lo[3];   // coordinate-wise minimum of the particles

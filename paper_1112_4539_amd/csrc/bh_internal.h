@@ -71,6 +71,7 @@ struct WalkArgs {
   double eps2;
   double inv_theta;            // 1/theta when theta_group is null
   const WalkNode* wnodes;      // uniform theta: walk copy of the nodes (S and M32 precomputed)
+  const ThetaNode* tnodes;     // per-group theta, FP32: walk copy with l and s (same memory as wnodes)
   const float* theta_group;    // theta per 64-particle Morton group, may be null
   void* acc;                   // [n][3] caller order
   void* pot;                   // [n] caller order
@@ -124,6 +125,9 @@ hipError_t launch_mlp_grad(const float* P, const uint16_t* wb, const float* norm
                            const int32_t* idx, int batch, float* partial, float* grad, hipStream_t st);
 hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, float lr, float beta1, float beta2,
                            float eps, float c1, float c2, uint16_t* wb, hipStream_t st);
+
+// Walk copy of the nodes for per-group theta (FP32 walks).
+hipError_t launch_theta_copy(const Node* nodes, const Counts* counts, int cap, ThetaNode* tnodes, hipStream_t st);
 
 // Direct sum of Eq. (1) for a list of targets (caller indices).
 hipError_t launch_direct(bool f64, const void* pos, const void* mass, int n, const int64_t* targets, int nt,

@@ -119,9 +119,37 @@ hipError_t launch_mac_size(const Node* nodes, const Counts* counts, int cap, dou
   return hipGetLastError();
 }
 
-// What a step needs of a node, from the walk copy (uniform theta) or from the
-// plain node (per-group theta: S formed from l and s per lane).
-template <bool kPlain>
+__global__ __launch_bounds__(256) void k_theta_copy(const Node* __restrict__ nodes, const Counts* __restrict__ cnt,
+                                                    int cap, ThetaNode* __restrict__ tnodes) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cap || c >= cnt->n_nodes) return;
+  const Node nd = nodes[c];
+  const bool leaf = nd.meta & 1;
+  ThetaNode w;
+  w.cx = nd.cx;
+  w.cy = nd.cy;
+  w.cz = nd.cz;
+  w.l = leaf ? 0.0 : nd.l;
+  w.M32 = (float)nd.M;
+  w.next = nd.next;
+  w.first = nd.first;
+  w.count = nd.count;
+  w.s = leaf ? 0.0 : nd.s;
+  w.meta = nd.meta;
+  w.pad = 0;
+  tnodes[c] = w;
+}
+
+hipError_t launch_theta_copy(const Node* nodes, const Counts* counts, int cap, ThetaNode* tnodes, hipStream_t st) {
+  if (cap <= 0) return hipSuccess;
+  k_theta_copy<<<(cap + 255) / 256, 256, 0, st>>>(nodes, counts, cap, tnodes);
+  return hipGetLastError();
+}
+
+// What a step needs of a node: the walk copy for one theta (S and the FP32
+// mass precomputed), the per-group-theta copy (FP32: l, s and the FP32 mass),
+// or the plain node (FP64 per-group theta).
+template <bool kF64, bool kPlain>
 struct StepNode;
 // Records are read through the constant address space: the node arrays are
 // not written while a walk runs, and saying so lets the compiler keep the
@@ -132,21 +160,28 @@ template <typename Rec>
 __device__ __forceinline__ Rec const_load(const Rec* base, int c) {
   const BH_CONST Rec* p = (const BH_CONST Rec*)(uintptr_t)base + (uint32_t)c;
   Rec r;
-  if constexpr (sizeof(Rec) == sizeof(WalkNode) && std::is_same<Rec, WalkNode>::value) {
+  if constexpr (std::is_same<Rec, WalkNode>::value) {
     r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.S = p->S; r.M32 = p->M32; r.pad = 0; r.M = p->M;
+  } else if constexpr (std::is_same<Rec, ThetaNode>::value) {
+    r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.l = p->l; r.M32 = p->M32; r.s = p->s; r.pad = 0;
   } else {
     r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.M = p->M; r.l = p->l; r.s = p->s;
   }
   r.next = p->next; r.first = p->first; r.count = p->count; r.meta = p->meta;
   return r;
 }
-template <>
-struct StepNode<false> {
+template <bool kF64>
+struct StepNode<kF64, false> {
   const WalkNode* base;
   __device__ __forceinline__ WalkNode load(int c) const { return const_load(base, c); }
 };
 template <>
-struct StepNode<true> {
+struct StepNode<false, true> {
+  const ThetaNode* base;
+  __device__ __forceinline__ ThetaNode load(int c) const { return const_load(base, c); }
+};
+template <>
+struct StepNode<true, true> {
   const Node* base;
   __device__ __forceinline__ Node load(int c) const { return const_load(base, c); }
 };
@@ -246,7 +281,8 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
   const int c = C.c;
   if constexpr (kStats) ++C.steps;
   const int nnext = max(cur.next, c + 1);
-  if constexpr (!kF64 && !kPlain) {
+  constexpr bool kTheta = std::is_same<Rec, ThetaNode>::value;
+  if constexpr (!kF64) {
     // Keep the FP32 mass in the step's first batch of scalar loads: it is used
     // only by the term, and a load left to the term's branch would cost the
     // step a second memory round trip.  (An empty statement that takes the
@@ -271,7 +307,10 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
     // Opening test of Eq. (2) in FP64.
     d2[t] = fma(dz[t], dz[t], fma(dy[t], dy[t], dx[t] * dx[t]));
     double S;
-    if constexpr (kPlain) {
+    if constexpr (kTheta) {
+      const double u = fma(cur.l, T.inv_theta, cur.s);  // a leaf: l = s = 0, S = 0
+      S = u * u;
+    } else if constexpr (kPlain) {
       const double u = fma(cur.l, T.inv_theta, cur.s);
       S = (cur.meta & 1) ? -1.0 : u * u;
     } else {
@@ -295,7 +334,7 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
     bucket_step<kF64, kT, kMode, kSoft>(a, C, cur);
   } else {
     R tm;
-    if constexpr (kF64 || kPlain) tm = (R)cur.M; else tm = (R)cur.M32;
+    if constexpr (kF64) tm = (R)cur.M; else tm = (R)cur.M32;
     const bool cell = (cur.meta & 1) == 0;
 #pragma unroll
     for (int t = 0; t < kT; ++t) {
@@ -347,13 +386,13 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 // array, and every step moves the cursor forward or stays on a leaf for at most
 // its particle count.
 template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
-__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
+__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
                                                  int end) {
   while (C.c < end) walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, wn.load(C.c));
 }
 
 template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
-__device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
+__device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
                                               uint4 (*pf)[8], int end) {
   using Rec = decltype(wn.load(0));
   const int cap = 2 * a.n;
@@ -380,7 +419,7 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kPlain
 // The clusters klo..khi of a wave, one subtree after the other; targets of the
 // other clusters stay idle (skip past the subtree).
 template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, bool kLds>
-__device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kPlain> wn, Cursor<kF64, kT>& C,
+__device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
                                               uint4 (*pf)[8], const int (&kc)[kT], int klo, int khi) {
   const int cap = 2 * a.n;
   for (int k = klo; k <= khi; ++k) {
@@ -455,8 +494,10 @@ __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (
   }
   klo = uniform(klo);
   khi = uniform(khi);
-  StepNode<kGroupTheta> wn;
-  if constexpr (kGroupTheta) wn.base = a.nodes; else wn.base = a.wnodes;
+  StepNode<kF64, kGroupTheta> wn;
+  if constexpr (kGroupTheta && kF64) wn.base = a.nodes;
+  else if constexpr (kGroupTheta) wn.base = a.tnodes;
+  else wn.base = a.wnodes;
   // Waves split between the two node paths (scalar cache / LDS copies) so
   // that neither the scalar cache nor instruction issue alone sets the pace;
   // the share taking the LDS path is a launch parameter (results identical).
