@@ -186,7 +186,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.ps = t->w.ps;
   a.perm = t->w.idx_a;
   a.order = t->target_order == 1 ? t->rank : nullptr;
-  a.scid = t->w.scid;
+  a.scid = t->n_seg > 1 ? t->w.scid : nullptr;  // (a single tree keeps no cluster ids)
   a.croot = t->w.croot;
   a.seg_off = t->w.seg_off;
   a.n_seg = (int)t->n_seg;
@@ -553,7 +553,8 @@ int bh_features(const bh_tree* t, float* X, void* stream) {
   if (!t) return fail(BH_EINVAL, "null tree");
   if (t->n == 0) return BH_OK;
   if (!X || !aligned(X, 4)) return fail(BH_EINVAL, "X must be a non-null device array of floats");
-  hipError_t e = bh::launch_features(t->prec == BH_FP64, t->w.nodes, t->w.ps, t->w.cube, t->w.scid, t->w.croot,
+  hipError_t e = bh::launch_features(t->prec == BH_FP64, t->w.nodes, t->w.ps, t->w.cube,
+                                     t->n_seg > 1 ? t->w.scid : nullptr, t->w.croot,
                                      t->w.seg_off, (int)t->n_seg, (int)t->n, X, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "launching the feature pass");
   return BH_OK;

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, int n, 
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int k = K > 1 ? seg_of(off, K, i) : 0;
-  seg[i] = k;
+  if (seg) seg[i] = k;
   const Cube* cube = cubes + k;
   const double sc = cube->scale;
   uint64_t q[3];
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ pos, const
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int64_t j = perm[k];
-  scid[k] = seg[j];
+  if (scid) scid[k] = seg[j];
   T4 v;
   v.x = pos[3 * j];
   v.y = pos[3 * j + 1];
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256) void k_unique_flags(const uint64_t* __restrict
                                                       int32_t* __restrict__ flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  flag[i] = (i == 0 || keys[i] != keys[i - 1] || scid[i] != scid[i - 1]) ? 1 : 0;
+  flag[i] = (i == 0 || keys[i] != keys[i - 1] || (scid && scid[i] != scid[i - 1])) ? 1 : 0;
 }
 
 __global__ __launch_bounds__(256) void k_unique_write(const uint64_t* __restrict__ keys,
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256) void k_unique_write(const uint64_t* __restrict
   if (flag[i]) {
     ukey[uid[i]] = keys[i];
     ustart[uid[i]] = i;
-    ucid[uid[i]] = scid[i];
+    if (ucid) ucid[uid[i]] = scid[i];
   }
   if (i == n - 1) {
     int U = uid[i] + flag[i];
@@ -513,8 +513,8 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
     rep[j] = 0;
     return;
   }
-  const int cj = ucid[j];
-  if (ucid[j + 1] != cj) {
+  const int cj = ucid ? ucid[j] : 0;
+  if (ucid && ucid[j + 1] != cj) {
     split[j] = -1;
     rep[j] = 0;
     return;
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
   const uint64_t kj = ukey[j], kj1 = ukey[j + 1];
   const int s = split_level(kj, kj1);
   split[j] = s;
-  auto in_cell = [&](int m, uint64_t ref) { return ucid[m] == cj && same_cell(ukey[m], ref, s); };
+  auto in_cell = [&](int m, uint64_t ref) { return (!ucid || ucid[m] == cj) && same_cell(ukey[m], ref, s); };
   // first key of the cell: smallest f <= j with same_cell(ukey[f], kj, s)
   int lo = j, step = 1;
   while (true) {
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict
   const int s = ilevel[v], f = ifirst[v], l = ilast[v];
   const int pre = f + nexcl[f] + __popc(lmask[f] & ((1u << s) - 1u));
   ipre[v] = pre;
-  const Cube* cube = cubes + ucid[f];
+  const Cube* cube = cubes + (ucid ? ucid[f] : 0);
   Node nd;
   nd.cx = nd.cy = nd.cz = 0.0;
   nd.M = 0.0;
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
   if (x >= nmax || x >= U) return;
   const int pre = x + nexcl[x] + nstart[x];
   const int first = ustart[x], count = ustart[x + 1] - first;
-  const Cube* cube = cubes + ucid[x];
+  const Cube* cube = cubes + (ucid ? ucid[x] : 0);
   // a leaf sits one level below the deeper of its two neighbour splits (split
   // -1 marks a cluster edge, so a cluster's only key is its level-0 root)
   int level;
@@ -706,7 +706,7 @@ __global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict_
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nmax || v >= cnt->n_internal || ilevel[v] != level) return;
   const int p = ipre[v];
-  const Cube* cube = cubes + ucid[ifirst[v]];
+  const Cube* cube = cubes + (ucid ? ucid[ifirst[v]] : 0);
   const int n_nodes = cnt->n_nodes;
   const int end = min(nodes[p].next, n_nodes);
   double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
@@ -766,7 +766,11 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
     k_bbox_seg<T><<<K, 256, 0, st>>>(pos, mass, w.seg_off, n, w.cube, w.counts);
   }
   // keys and stable sort by (cluster, key): 8 key passes, then the cluster digits
-  k_keys<T><<<nblk(n, 256), 256, 0, st>>>(pos, n, w.cube, w.seg_off, K, w.seg, w.key_a, w.idx_a);
+  // cluster ids are kept only for a forest (a single tree's are all 0)
+  int32_t* seg = K > 1 ? w.seg : nullptr;
+  int32_t* scid = K > 1 ? w.scid : nullptr;
+  int32_t* ucid = K > 1 ? w.ucid : nullptr;
+  k_keys<T><<<nblk(n, 256), 256, 0, st>>>(pos, n, w.cube, w.seg_off, K, seg, w.key_a, w.idx_a);
   const int ntiles = (n + kSortTile - 1) / kSortTile;
   int seg_passes = 0;
   for (unsigned r = (unsigned)(K - 1); r; r >>= 8) ++seg_passes;
@@ -789,15 +793,15 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
   }
   // the sorted data must end in key_a / idx_a
   if (kin != w.key_a) k_copy_kv<<<nblk(n, 256), 256, 0, st>>>(kin, vin, w.key_a, w.idx_a, n);
-  k_gather<T, T4><<<nblk(n, 256), 256, 0, st>>>(pos, mass, w.idx_a, w.seg, n, reinterpret_cast<T4*>(w.ps), w.scid);
+  k_gather<T, T4><<<nblk(n, 256), 256, 0, st>>>(pos, mass, w.idx_a, seg, n, reinterpret_cast<T4*>(w.ps), scid);
   // unique (cluster, key) pairs
-  k_unique_flags<<<nblk(n, 256), 256, 0, st>>>(w.key_a, w.scid, n, w.flag);
+  k_unique_flags<<<nblk(n, 256), 256, 0, st>>>(w.key_a, scid, n, w.flag);
   if ((e = scan_excl(w.flag, w.uid, n, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
-  k_unique_write<<<nblk(n, 256), 256, 0, st>>>(w.key_a, w.scid, n, w.flag, w.uid, w.ukey, w.ustart, w.ucid,
+  k_unique_write<<<nblk(n, 256), 256, 0, st>>>(w.key_a, scid, n, w.flag, w.uid, w.ukey, w.ustart, ucid,
                                                w.counts);
   k_croot_first<<<nblk(K + 1, 256), 256, 0, st>>>(w.seg_off, K, n, w.uid, w.counts, w.croot);
   // internal nodes
-  k_pairs<<<nblk(n, 256), 256, 0, st>>>(w.ukey, w.ucid, w.counts, w.split, w.flag, w.pf, w.pl, n);
+  k_pairs<<<nblk(n, 256), 256, 0, st>>>(w.ukey, ucid, w.counts, w.split, w.flag, w.pf, w.pl, n);
   if ((e = scan_excl(w.flag, w.uid, n, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
   k_fill_i32<<<nblk(n + 1, 256), 256, 0, st>>>(w.nstart, n + 1, 0);
   k_fill_i32<<<nblk(n + 1, 256), 256, 0, st>>>(reinterpret_cast<int32_t*>(w.lmask), n + 1, 0);
@@ -805,12 +809,12 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
                                                  w.ilast, w.nstart, w.lmask, n);
   if ((e = scan_excl(w.nstart, w.nexcl, n + 1, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
   k_croot_final<<<nblk(K + 1, 256), 256, 0, st>>>(K, w.nexcl, w.croot);
-  k_nodes_internal<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ucid, w.ilevel, w.ifirst, w.ilast,
+  k_nodes_internal<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.ilevel, w.ifirst, w.ilast,
                                                      w.nstart, w.nexcl, w.lmask, w.ustart, w.ipre, w.nodes, n);
-  k_nodes_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ucid, w.split, w.nstart, w.nexcl, w.ustart,
+  k_nodes_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.split, w.nstart, w.nexcl, w.ustart,
                                                  reinterpret_cast<const T4*>(w.ps), w.nodes, w.Mx, n);
   for (int level = kLevels - 1; level >= 0; --level)
-    k_moments_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, w.ucid, w.ilevel, w.ifirst, w.ipre, w.ukey,
+    k_moments_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.ilevel, w.ifirst, w.ipre, w.ukey,
                                                   w.nodes, w.Mx, level, n);
   return hipGetLastError();
 }

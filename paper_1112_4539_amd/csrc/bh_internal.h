@@ -63,7 +63,7 @@ struct WalkArgs {
   const void* ps;              // float4 / double4 particles in Morton order
   const int32_t* perm;         // Morton position -> caller index
   const int32_t* order;        // optional target order (Morton positions), may be null
-  const int32_t* scid;         // Morton position -> cluster
+  const int32_t* scid;         // Morton position -> cluster (null for a single tree)
   const int32_t* croot;        // [K+1] preorder range of each cluster's subtree
   const int64_t* seg_off;      // [K+1] caller offsets of the clusters (list words are cluster-relative)
   int n_seg;

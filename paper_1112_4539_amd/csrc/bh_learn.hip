@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_features(const Node* __restrict__ nodes
   const int a = 64 * g;
   if (a >= n) return;
   const int b = min(n, a + 64);
-  const int k = min(max(scid[a], 0), n_seg - 1);
+  const int k = scid ? min(max(scid[a], 0), n_seg - 1) : 0;
   const double L = cubes[k].L;
   const int64_t nk64 = seg_off[k + 1] - seg_off[k];
   const double Nk = (double)(nk64 > 0 ? nk64 : 1);

@@ -479,7 +479,7 @@ __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (
     guard_l = guard_l || (valid && T.inv_theta < 1.0);
     // Clusters of the wave's targets: a wave usually lies inside one cluster;
     // one that straddles cluster edges walks each cluster's subtree in turn.
-    kc[t] = valid ? min(max(a.scid[T.i], 0), a.n_seg - 1) : 0;
+    kc[t] = (valid && a.scid) ? min(max(a.scid[T.i], 0), a.n_seg - 1) : 0;
     if (valid) {
       klo = min(klo, kc[t]);
       khi = max(khi, kc[t]);
