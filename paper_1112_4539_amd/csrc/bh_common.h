@@ -39,7 +39,7 @@ struct alignas(64) Node {
 static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
 
 // The walk's copy of a node for one uniform theta: a cell carries its squared
-// opening size S = (l/theta + s)^2 (a leaf -1), and the mass also rounded to
+// opening size S = (l/theta + s)^2 (a leaf 0), and the mass also rounded to
 // FP32.  The fields one FP32 step reads (centre, S, M32, next, first, count,
 // meta) are the first 52 bytes, the FP32 mass beside the integers, so that
 // they arrive in one batch of scalar loads.

@@ -96,13 +96,14 @@ __global__ __launch_bounds__(256) void k_mac_size(const Node* __restrict__ nodes
   const Node nd = nodes[c];
   const double u = fma(nd.l, inv_theta, nd.s);
   WalkNode w;
-  // a leaf is always "accepted" by the opening test (S = -1 < d^2): its
-  // particle is used unless it is the target itself
+  // A leaf's S is 0: every other particle passes (d^2 > 0, since particles at
+  // the same position share a leaf of several particles), and the target's own
+  // leaf fails (its position is the target's, exactly: d^2 = 0).
   w.cx = nd.cx;
   w.cy = nd.cy;
   w.cz = nd.cz;
   w.M = nd.M;
-  w.S = (nd.meta & 1) ? -1.0 : u * u;
+  w.S = (nd.meta & 1) ? 0.0 : u * u;
   w.M32 = (float)nd.M;
   w.pad = 0;
   w.next = nd.next;
@@ -257,12 +258,12 @@ __device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>&
 }
 
 // One step of a walk at node `cur` (index C.c).  A cell and a one-particle
-// leaf take the same path: the walk copy gives a leaf S = -1, so its opening
-// test always passes, and a node whose first particle is the target itself is
-// never used (for a cell that holds the target the test fails by itself when
-// theta <= 1: d <= (sqrt(3)/2) l + s < l/theta + s, a margin of 0.13 l that no
-// rounding reaches).  kGuard: some target of the wave has theta > 1, so a cell
-// holding the target is excluded by its particle range instead.
+// leaf take the same path, and the opening test alone decides: the walk copies
+// give a leaf S = 0, which every other particle passes (d^2 > 0) and the
+// target's own leaf fails (d^2 = 0 exactly); a cell that holds the target
+// fails the test when theta <= 1 (d <= (sqrt(3)/2) l + s < l/theta + s, a
+// margin of 0.13 l that no rounding reaches).  kGuard: some target of the wave
+// has theta > 1, so a cell holding the target is excluded by its particle range.
 //
 // A target that uses the node adds its term and skips the node's subtree
 // (next(c); for a leaf that is c + 1 anyway); the cursor moves to c + 1 if an
@@ -312,20 +313,22 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
       S = u * u;
     } else if constexpr (kPlain) {
       const double u = fma(cur.l, T.inv_theta, cur.s);
-      S = (cur.meta & 1) ? -1.0 : u * u;
+      S = (cur.meta & 1) ? 0.0 : u * u;
     } else {
       S = cur.S;
     }
     const bool pd = d2[t] > S;
-    const bool ns = kGuard ? (unsigned)(T.i - cur.first) >= (unsigned)cur.count : T.i != cur.first;
-    use[t] = act && pd && ns;
-    // the same tests as lane masks, straight from the compares (ordered >,
-    // unsigned >= / !=) -- a ballot of the combined flag would first turn it
-    // into a number
-    const uint64_t m_pd = __builtin_amdgcn_fcmp(d2[t], S, 2);
-    const uint64_t m_ns = kGuard ? __builtin_amdgcn_uicmp((unsigned)(T.i - cur.first), (unsigned)cur.count, 35)
-                                 : __builtin_amdgcn_uicmp((unsigned)T.i, (unsigned)cur.first, 33);
-    m_open |= m_act & ~(m_pd & m_ns);
+    // the same test as a lane mask, straight from the compare (ordered >) --
+    // a ballot of a combined flag would first turn it into a number
+    uint64_t m_pass = __builtin_amdgcn_fcmp(d2[t], S, 2);
+    if constexpr (kGuard) {
+      const bool ns = (unsigned)(T.i - cur.first) >= (unsigned)cur.count;
+      use[t] = act && pd && ns;
+      m_pass &= __builtin_amdgcn_uicmp((unsigned)(T.i - cur.first), (unsigned)cur.count, 35);  // unsigned >=
+    } else {
+      use[t] = act && pd;
+    }
+    m_open |= m_act & ~m_pass;
   }
   // (the test above runs for every node, so that the whole record is read at
   // the top of the step; a leaf of several particles then goes its own way --
