@@ -141,12 +141,24 @@ def test_lists_and_forces_plummer4k_fp32(bh, theta, tpl):
     assert pot_err(pot, w["pot"]).max() <= F32_TOL
 
 
+@pytest.mark.parametrize("prec,theta", [("fp64", 1.1), ("fp32", 1.1), ("fp32", 1.15)])
+def test_lists_theta_above_one(bh, prec, theta):
+    """theta in (1, 2/sqrt(3)): a cell holding the target can pass the opening
+    test, and the walk must exclude it by its particle range (the guarded path)."""
+    say(f"[walk] plummer4k {prec} theta={theta} full list dump (guarded walk)")
+    pos, mass = inputs.plummer(4096, 0)
+    acc, pot, w = _walk_compare(bh, pos, mass, prec, theta, 0.01, maxlen=4096)
+    tol = F32_TOL if prec == "fp32" else F64_TOL
+    assert force_err(acc, w["acc"], w["amag"]).max() <= tol
+    assert pot_err(pot, w["pot"]).max() <= tol
+
+
 @pytest.mark.parametrize("tpl", [1, 2])
 def test_theta_per_group(bh, tpl):
     say(f"[walk] per-group theta, clumpy 50k fp32, {tpl} targets per lane")
     pos, mass = inputs.clumpy(50_000, 31)
     g = (len(pos) + 63) // 64
-    tg = np.random.default_rng(3).uniform(0.2, 1.0, g).astype(np.float32)
+    tg = np.random.default_rng(3).uniform(0.2, 1.15, g).astype(np.float32)
     acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.5, 1e-4, theta_group=tg, tpl=tpl)
     e = force_err(acc, w["acc"], w["amag"])
     say(f"  max err {e.max():.3e}")
