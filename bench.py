@@ -282,6 +282,40 @@ def learned_bench(args, bh, inputs):
     print(json.dumps(line), flush=True)
 
 
+def cube_bench(args, bh, inputs):
+    """The paper's uniform-cube run for context: N = 1,048,576 particles uniform in the unit cube
+    (seed 5, equal masses), theta = 0.6, FP32; the whole step (build + walk) is timed.  The
+    paper's softening for this run is not stated; eps = 1e-3 here."""
+    n, theta, eps = 1 << 20, 0.6, 1e-3
+    rng = np.random.default_rng(5)
+    pos = rng.random((n, 3))
+    dev = torch.device("cuda:0")
+    gpos = torch.tensor(pos.astype(np.float32), device=dev)
+    gmass = torch.full((n,), 1.0 / n, dtype=torch.float32, device=dev)
+    ws = torch.empty(bh.workspace_bytes(n, bh.FP32), dtype=torch.uint8, device=dev)
+    acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((n,), dtype=torch.float32, device=dev)
+    T = bh.Tree(gpos, gmass, workspace=ws)
+    inter = int(T.walk_stats(theta, eps)["counts"].to(torch.int64).sum().item())
+    for _ in range(args.warmup):
+        bh.Tree(gpos, gmass, workspace=ws).forces(theta, eps, acc, pot)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        bh.Tree(gpos, gmass, workspace=ws).forces(theta, eps, acc, pot)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    line = {"metric": "forces/s, uniform cube N=1M, theta 0.6 (the paper's context run)",
+            "value": n / (ms * 1e-3), "unit": "forces/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"uniform cube N={n}, seed 5, theta={theta}, eps={eps}, FP32",
+                       "interactions_per_step": inter, "interactions_per_s": inter / (ms * 1e-3)}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +350,8 @@ def main():
         return sweep_bench(args, bh, inputs)
     if args.workload == "learned":
         return learned_bench(args, bh, inputs)
+    if args.workload == "cube1m":
+        return cube_bench(args, bh, inputs)
 
     if args.copy_calib > 0:
         # a plain copy of known size: reads and writes exactly MIB MiB each
