@@ -8,16 +8,18 @@
 //     then continue at next(c);
 //   * otherwise open the cell: continue at more(c) = c + 1.
 //
-// How it runs on CDNA: one wavefront walks 64 Morton-consecutive targets
-// together.  The wave keeps one cursor c over the preorder node array; lane i
-// is active at c iff c >= skip_i, where skip_i = next of the last cell lane i
-// accepted.  At an internal node every active lane evaluates the opening test;
-// accepting lanes add the cell term (masked) and set skip_i = next(c).  The
-// cursor goes to c+1 if any active lane opened c (wave ballot), else to
-// next(c).  Every lane therefore meets exactly the nodes of its own
-// single-particle walk, in the same order, so lists and summation order do not
-// depend on how targets are grouped.  Node records are wave-uniform and are
-// read with scalar loads; there is no divergence in the traversal itself.
+// How it runs on CDNA: one wavefront walks 64 (or 128: two per lane)
+// Morton-consecutive targets together.  The wave keeps one cursor c over the
+// preorder node array; a target is active at c iff c >= its skip pointer, the
+// next of the last cell it accepted.  Every active target evaluates the
+// opening test; the ones that pass add the term (masked) and skip the node's
+// subtree.  The cursor goes to c+1 if an active target opened c (a lane mask
+// from the compare), else to next(c).  Every target therefore meets exactly
+// the nodes of its own single-particle walk, in the same order, so lists and
+// summation order do not depend on how targets are grouped.  Node records are
+// wave-uniform and are read with scalar loads; there is no divergence in the
+// traversal itself.  In a forest a wave walks, in turn, the subtree of every
+// cluster its targets belong to.
 //
 // Precision (FP32 variant): positions and masses are FP32.  The opening test
 // runs in FP64 on the FP64 centre of mass and the exactly widened position,
@@ -25,8 +27,8 @@
 // the FP64 reference walk.  The same FP64 offset and d^2 feed the term:
 // r^2 + eps^2 is rounded once to FP32, the inverse square root is v_rsq_f32,
 // and the contributions are accumulated in FP64 (on CDNA4 FP64 add and FMA
-// issue at the unpacked FP32 rate).  The FP64 variant evaluates every term
-// exactly as the reference definition (IEEE sqrt and division, no
+// issue at nearly the unpacked FP32 rate).  The FP64 variant evaluates every
+// term exactly as the reference definition (IEEE sqrt and division, no
 // contraction) and accumulates in FP64.
 #include "bh_internal.h"
 
