@@ -220,8 +220,8 @@ struct Cursor {
 
 // A step at a leaf of several coincident-key particles (rare): one of its
 // particles per step, the cursor staying on the leaf until they are done.
-template <bool kF64, int kT, int kMode, bool kSoft, typename Rec>
-__device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& cur) {
+template <bool kF64, int kT, int kMode, bool kSoft, typename Rec, typename Fetch>
+__device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& cur, Fetch&& fetch) {
   using R4 = typename std::conditional<kF64, double4, float4>::type;
   constexpr bool kStats = kMode != kWalkForces;
   const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
@@ -231,6 +231,8 @@ __device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>&
     C.kend = C.k + min(max(cur.count, 0), a.n - C.k);
   }
   const int kk = min(C.k, a.n - 1);
+  const bool more = C.k + 1 < C.kend;
+  fetch(more ? c : c + 1);
   const R4 q = ps[kk];
 #pragma unroll
   for (int t = 0; t < kT; ++t) {
@@ -251,7 +253,8 @@ __device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>&
       }
     }
   }
-  if (++C.k < C.kend) {
+  if (more) {
+    ++C.k;
     C.c = c;
   } else {
     C.k = C.kend = 0;
@@ -270,8 +273,13 @@ __device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>&
 // A target that uses the node adds its term and skips the node's subtree
 // (next(c); for a leaf that is c + 1 anyway); the cursor moves to c + 1 if an
 // active target did not use the node, else to next(c).
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, typename Rec>
-__device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& rec) {
+//
+// `fetch` is called with the next cursor as soon as the opening decisions fix
+// it, before the terms are evaluated: the caller issues the next record's load
+// there, and its latency overlaps the terms instead of heading the next step.
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, typename Rec,
+          typename Fetch>
+__device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& rec, Fetch&& fetch) {
   // The record was read from LDS by every lane; its integer fields steer the
   // wave's control flow, so take them as wave-uniform values.
   Rec cur = rec;
@@ -336,8 +344,10 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
   // the top of the step; a leaf of several particles then goes its own way --
   // kBucket: the tree has such leaves, known per walk from the build's counts)
   if (kBucket && (cur.meta & 2)) {
-    bucket_step<kF64, kT, kMode, kSoft>(a, C, cur);
+    bucket_step<kF64, kT, kMode, kSoft>(a, C, cur, fetch);
   } else {
+    const int cn = m_open ? c + 1 : nnext;
+    fetch(cn);
     R tm;
     if constexpr (kF64) tm = (R)cur.M; else tm = (R)cur.M32;
     const bool cell = (cur.meta & 1) == 0;
@@ -361,7 +371,7 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
         }
       }
     }
-    C.c = m_open ? c + 1 : nnext;
+    C.c = cn;
   }
 }
 
@@ -385,7 +395,8 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 }
 
 // The plain form: each step reads its node with scalar loads (the record is
-// wave-uniform), one round trip per step.
+// wave-uniform), one round trip per step, issued by the previous step as soon
+// as it knows the cursor.
 // Both forms walk the subtree [C.c, end) of one cluster; `end` is clamped to
 // the node capacity, so a corrupted record can never send the cursor out of the
 // array, and every step moves the cursor forward or stays on a leaf for at most
@@ -393,7 +404,15 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
 __device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
                                                  int end) {
-  while (C.c < end) walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, wn.load(C.c));
+  using Rec = decltype(wn.load(0));
+  const int last = 2 * a.n - 1;  // the node arrays hold 2n records
+  Rec rec = wn.load(C.c);
+  while (C.c < end) {
+    Rec nxt;
+    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, rec,
+                                                               [&](int cn) { nxt = wn.load(min(cn, last)); });
+    rec = nxt;
+  }
 }
 
 template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
@@ -413,7 +432,7 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kF64, 
     const Rec rec = reinterpret_cast<const Rec*>(pf[buf])[slot];
     const int nnext = max(uniform(rec.next), c + 1);
     fetch_pair(wn.base, min(c + 1, cap - 1), min(nnext, cap - 1), lane, pf[buf ^ 1]);
-    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, rec);
+    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, rec, [](int) {});
     if (C.c != c) {  // moved on (a leaf of several particles keeps the cursor)
       slot = C.c == c + 1 ? 0 : 1;
       buf ^= 1;
