@@ -52,20 +52,29 @@ __device__ __forceinline__ int remap_block(int b, int nb, int chunk) {
 // in FP64 (CDNA4 issues FP64 add and FMA at the FP32 rate, so this costs no
 // more than FP32 sums with periodic compensation, and leaves no summation
 // error worth counting).
+struct MixedTerm {
+  double mr3, mr;  // m r^-3 and m r^-1
+};
 struct AccMixed {
   double ax, ay, az, p;
   __device__ void init() { ax = ay = az = p = 0.0; }
   template <bool kSoft>
-  __device__ __forceinline__ void term(double dx, double dy, double dz, double d2, float m, double eps2) {
+  static __device__ __forceinline__ MixedTerm prep(double d2, float m, double eps2) {
     const float r2 = (float)(d2 + eps2);
     // r2 == 0 only for a coincident pair without softening: that pair adds nothing
     const float ri = kSoft ? __builtin_amdgcn_rsqf(r2) : ((r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f);
     const float mr = m * ri;
-    const double mr3 = (double)((mr * ri) * ri);
-    ax = fma(mr3, dx, ax);
-    ay = fma(mr3, dy, ay);
-    az = fma(mr3, dz, az);
-    p -= (double)mr;
+    return MixedTerm{(double)((mr * ri) * ri), (double)mr};
+  }
+  __device__ __forceinline__ void add(const MixedTerm& q, double dx, double dy, double dz) {
+    ax = fma(q.mr3, dx, ax);
+    ay = fma(q.mr3, dy, ay);
+    az = fma(q.mr3, dz, az);
+    p -= q.mr;
+  }
+  template <bool kSoft>
+  __device__ __forceinline__ void term(double dx, double dy, double dz, double d2, float m, double eps2) {
+    add(prep<kSoft>(d2, m, eps2), dx, dy, dz);
   }
 };
 
@@ -351,6 +360,17 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
     R tm;
     if constexpr (kF64) tm = (R)cur.M; else tm = (R)cur.M32;
     const bool cell = (cur.meta & 1) == 0;
+    // FP32: the term's factors are formed for every lane ahead of the masked
+    // sums (a VALU instruction costs the same with lanes masked off), so
+    // that they overlap the cursor's scalar work instead of following it.
+    MixedTerm q[kT];
+    if constexpr (!kF64) {
+#pragma unroll
+      for (int t = 0; t < kT; ++t) {
+        q[t] = AccMixed::prep<kSoft>(d2[t], tm, a.eps2);
+        asm volatile("" : "+v"(q[t].mr3), "+v"(q[t].mr));
+      }
+    }
 #pragma unroll
     for (int t = 0; t < kT; ++t) {
       Target<kF64>& T = C.t[t];
@@ -358,7 +378,7 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
         if constexpr (kF64) {
           T.acc.term(dx[t], dy[t], dz[t], tm, a.eps2);
         } else {
-          T.acc.template term<kSoft>(dx[t], dy[t], dz[t], d2[t], tm, a.eps2);
+          T.acc.add(q[t], dx[t], dy[t], dz[t]);
         }
         T.skip = nnext;
         if constexpr (kStats) {
