@@ -117,7 +117,9 @@ __global__ __launch_bounds__(256) void k_mac_size(const Node* __restrict__ nodes
   w.S = (nd.meta & 1) ? 0.0 : u * u;
   w.M32 = (float)nd.M;
   w.pad = 0;
-  w.next = nd.next;
+  // next(c) kept inside (c, cap]: the walk then moves forward and reads at
+  // most one record past the last without checking
+  w.next = min(max(nd.next, c + 1), cap);
   w.first = nd.first;
   w.count = nd.count;
   w.meta = nd.meta;
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(256) void k_theta_copy(const Node* __restrict__ nod
   w.cz = nd.cz;
   w.l = leaf ? 0.0 : nd.l;
   w.M32 = (float)nd.M;
-  w.next = nd.next;
+  w.next = min(max(nd.next, c + 1), cap);  // as in the uniform-theta copy
   w.first = nd.first;
   w.count = nd.count;
   w.s = leaf ? 0.0 : nd.s;
@@ -300,7 +302,10 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
   constexpr bool kStats = kMode != kWalkForces;
   const int c = C.c;
   if constexpr (kStats) ++C.steps;
-  const int nnext = max(cur.next, c + 1);
+  // (the walk copies hold next(c) in (c, cap] already; the plain nodes of the
+  // FP64 per-group-theta walk are taken as they are and clamped here)
+  constexpr bool kRaw = std::is_same<Rec, Node>::value;
+  const int nnext = kRaw ? max(cur.next, c + 1) : cur.next;
   constexpr bool kTheta = std::is_same<Rec, ThetaNode>::value;
   if constexpr (!kF64) {
     // Keep the FP32 mass in the step's first batch of scalar loads: it is used
@@ -425,12 +430,16 @@ template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bo
 __device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
                                                  int end) {
   using Rec = decltype(wn.load(0));
-  const int last = 2 * a.n - 1;  // the node arrays hold 2n records
+  // The next record is read before the loop test: the walk copies have a spare
+  // record at index cap = 2n (their next pointers stay <= cap); the plain node
+  // array is read at most at its last record.
+  constexpr bool kRaw = std::is_same<Rec, Node>::value;
+  const int last = 2 * a.n - 1;
   Rec rec = wn.load(C.c);
   while (C.c < end) {
     Rec nxt;
-    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, C, rec,
-                                                               [&](int cn) { nxt = wn.load(min(cn, last)); });
+    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(
+        a, C, rec, [&](int cn) { nxt = wn.load(kRaw ? min(cn, last) : cn); });
     rec = nxt;
   }
 }
