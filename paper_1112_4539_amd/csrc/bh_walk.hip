@@ -435,12 +435,15 @@ __device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kF6
   // array is read at most at its last record.
   constexpr bool kRaw = std::is_same<Rec, Node>::value;
   const int last = 2 * a.n - 1;
-  Rec rec = wn.load(C.c);
+  // (two steps per iteration, the records alternating between two sets of
+  // registers, so that no step has to move the next record into place)
+  Rec ra = wn.load(C.c), rb;
   while (C.c < end) {
-    Rec nxt;
     walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(
-        a, C, rec, [&](int cn) { nxt = wn.load(kRaw ? min(cn, last) : cn); });
-    rec = nxt;
+        a, C, ra, [&](int cn) { rb = wn.load(kRaw ? min(cn, last) : cn); });
+    if (C.c >= end) break;
+    walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(
+        a, C, rb, [&](int cn) { ra = wn.load(kRaw ? min(cn, last) : cn); });
   }
 }
 
