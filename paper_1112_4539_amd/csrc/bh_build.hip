@@ -353,8 +353,13 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __rest
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = (int32_t)h[threadIdx.x];
 }
 
-// Stable scatter: items of a tile are ranked in input order; within a wave the
-// rank among equal digits comes from 8 ballots (one per digit bit).
+// Stable scatter through LDS.  Each wave takes a contiguous quarter of the
+// tile and ranks its items in input order (the rank among equal digits within
+// 64 items comes from 8 ballots, one per digit bit), after per-wave digit
+// counts have given every wave its starting slot per digit; the items are
+// placed in LDS sorted by digit, and the tile then leaves in that order, so
+// that consecutive lanes write consecutive addresses of one digit's run
+// instead of 8- and 4-byte pieces all over the output.
 template <bool kSeg>
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                              const int32_t* __restrict__ vin,
@@ -362,46 +367,97 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __r
                                                              uint64_t* __restrict__ kout,
                                                              int32_t* __restrict__ vout, int n, int shift,
                                                              const int32_t* __restrict__ offs, int ntiles) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[kSortThreads / 64][256];
+  constexpr int kWaves = kSortThreads / 64;
+  constexpr int kPerWave = kSortTile / kWaves;
+  __shared__ uint64_t lkey[kSortTile];
+  __shared__ int32_t lval[kSortTile];
+  __shared__ uint8_t ldig[kSortTile];
+  __shared__ uint32_t goff[256];          // output position of the tile's first item of each digit
+  __shared__ uint32_t loff[256];          // tile position of the first item of each digit
+  __shared__ uint32_t wslot[kWaves][256]; // per wave: its counts, then its next slot per digit
+  __shared__ uint32_t wsum[kWaves];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  base[t] = (uint32_t)offs[(int64_t)t * ntiles + blockIdx.x];
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int m = (int)min((int64_t)kSortTile, (int64_t)n - tile0);  // items in this tile
+  goff[t] = (uint32_t)offs[(int64_t)t * ntiles + blockIdx.x];
 #pragma unroll
-  for (int k = 0; k < kSortThreads / 64; ++k) wcnt[k][t] = 0;
+  for (int k = 0; k < kWaves; ++k) wslot[k][t] = 0;
   __syncthreads();
+  // per-wave digit counts
+  for (int r = 0; r < kPerWave / 64; ++r) {
+    const int j = w * kPerWave + r * 64 + lane;
+    if (j < m) {
+      const int64_t i = tile0 + j;
+      atomicAdd(&wslot[w][digit_of<kSeg>(kSeg ? 0ull : kin[i], kSeg ? vin[i] : 0, seg, shift)], 1u);
+    }
+  }
+  __syncthreads();
+  {
+    // digit t: tile total, exclusive scan over digits, then each wave's first slot
+    uint32_t cw[kWaves];
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      cw[k] = wslot[k][t];
+      c += cw[k];
+    }
+    uint32_t x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    const uint32_t first = before + x - c;
+    loff[t] = first;
+    uint32_t run = first;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      wslot[k][t] = run;
+      run += cw[k];
+    }
+  }
+  __syncthreads();
+  // each wave places its items in input order; the slots it advances are its own
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t le = lt | (1ull << lane);
-  for (int r = 0; r < kSortItems; ++r) {
-    int64_t i = (int64_t)blockIdx.x * kSortTile + r * kSortThreads + t;
-    bool valid = i < n;
-    uint64_t key = valid ? kin[i] : 0ull;
-    int32_t val = valid ? vin[i] : 0;
-    uint32_t d = valid ? digit_of<kSeg>(key, val, seg, shift) : 0u;
+  for (int r = 0; r < kPerWave / 64; ++r) {
+    const int j = w * kPerWave + r * 64 + lane;
+    const bool valid = j < m;
+    const int64_t i = tile0 + j;
+    const uint64_t key = valid ? kin[i] : 0ull;
+    const int32_t val = valid ? vin[i] : 0;
+    const uint32_t d = valid ? digit_of<kSeg>(key, val, seg, shift) : 0u;
     uint64_t peers = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      bool bit = (d >> b) & 1u;
-      uint64_t m = ballot(bit);
-      peers &= bit ? m : ~m;
+      const bool bit = (d >> b) & 1u;
+      const uint64_t mk = ballot(bit);
+      peers &= bit ? mk : ~mk;
     }
-    uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && (peers & ~le) == 0ull) wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
     if (valid) {
-      uint32_t p = base[d] + rank;
-      for (int k = 0; k < w; ++k) p += wcnt[k][d];
-      kout[p] = key;
-      vout[p] = val;
+      const uint32_t q = wslot[w][d] + (uint32_t)__popcll(peers & lt);
+      lkey[q] = key;
+      lval[q] = val;
+      ldig[q] = (uint8_t)d;
     }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int k = 0; k < kSortThreads / 64; ++k) {
-      add += wcnt[k][t];
-      wcnt[k][t] = 0;
+    // (the wave's LDS operations take effect in program order: every lane has
+    // read its slot above before the last lane of each digit advances it)
+    if (valid && (peers & ~le) == 0ull) wslot[w][d] += (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // the tile in digit order: position j holds the (j - loff[d])-th item of digit d
+  for (int r = 0; r < kSortItems; ++r) {
+    const int j = r * kSortThreads + t;
+    if (j < m) {
+      const uint32_t d = ldig[j];
+      const uint32_t q = goff[d] + (uint32_t)j - loff[d];
+      kout[q] = lkey[j];
+      vout[q] = lval[j];
     }
-    base[t] += add;
-    __syncthreads();
   }
 }
 
