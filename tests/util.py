@@ -35,7 +35,8 @@ def tree_cases():
     """Small particle sets that exercise the tree build's corner cases."""
     rng = np.random.default_rng(5)
     cases = {}
-    for n in (1, 2, 3, 5, 8, 13, 16, 100, 1000):
+    # (8192 and 12289: whole sort tiles of 4096 keys, and several tiles with a ragged tail)
+    for n in (1, 2, 3, 5, 8, 13, 16, 100, 1000, 8192, 12289):
         cases[f"random{n}"] = rng.random((n, 3))
     p = rng.random((12, 3))
     p[5] = p[2]; p[9] = p[2]; p[7] = p[1]
