@@ -153,16 +153,20 @@ def test_lists_theta_above_one(bh, prec, theta):
     assert pot_err(pot, w["pot"]).max() <= tol
 
 
-@pytest.mark.parametrize("tpl", [1, 2])
-def test_theta_per_group(bh, tpl):
-    say(f"[walk] per-group theta, clumpy 50k fp32, {tpl} targets per lane")
+@pytest.mark.parametrize("prec,tpl", [("fp32", 1), ("fp32", 2), ("fp64", 1)])
+def test_theta_per_group(bh, prec, tpl):
+    """Per-group theta in [0.2, 1.15]: the FP32 walk reads its own node copy (l, s), the FP64 walk
+    the plain nodes; lists must equal the oracle's per-target-theta walk in both."""
+    say(f"[walk] per-group theta, clumpy 50k {prec}, {tpl} targets per lane")
     pos, mass = inputs.clumpy(50_000, 31)
     g = (len(pos) + 63) // 64
     tg = np.random.default_rng(3).uniform(0.2, 1.15, g).astype(np.float32)
-    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.5, 1e-4, theta_group=tg, tpl=tpl)
+    acc, pot, w = _walk_compare(bh, pos, mass, prec, 0.5, 1e-4, theta_group=tg, tpl=tpl)
     e = force_err(acc, w["acc"], w["amag"])
     say(f"  max err {e.max():.3e}")
-    assert e.max() <= F32_TOL
+    tol = F32_TOL if prec == "fp32" else F64_TOL
+    assert e.max() <= tol
+    assert pot_err(pot, w["pot"]).max() <= tol
 
 
 def test_direct_fp64_matches_definition(bh):
