@@ -184,20 +184,88 @@ __device__ __forceinline__ Rec const_load(const Rec* base, int c) {
   r.next = p->next; r.first = p->first; r.count = p->count; r.meta = p->meta;
   return r;
 }
+// The same loads with a 32-bit byte offset (walk copies below 4 GiB): the
+// scalar load then takes the offset in an SGPR, and the step saves the 64-bit
+// address arithmetic.  The record is read as vectors of dwords (a struct read
+// through a byte offset is split into many small loads); pieces a walk does
+// not use are dropped by the compiler.
+typedef unsigned v8u_t __attribute__((ext_vector_type(8)));
+typedef unsigned v2u_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double f64_of(v2u_t w) { return __builtin_bit_cast(double, w); }
+__device__ __forceinline__ const BH_CONST char* rec_at32(const void* base, int c) {
+  return (const BH_CONST char*)(uintptr_t)base + (uint32_t)c * 64u;
+}
+__device__ __forceinline__ WalkNode load32(const WalkNode* base, int c) {
+  const BH_CONST char* b = rec_at32(base, c);
+  const v8u_t w0 = *(const BH_CONST v8u_t*)b;             // cx, cy, cz, S
+  const v2u_t w1 = *(const BH_CONST v2u_t*)(b + 32);      // M32, next
+  const v2u_t w2 = *(const BH_CONST v2u_t*)(b + 40);      // first, count
+  const v2u_t w3 = *(const BH_CONST v2u_t*)(b + 48);      // meta, pad
+  const v2u_t w4 = *(const BH_CONST v2u_t*)(b + 56);      // M
+  WalkNode r;
+  r.cx = f64_of(w0.s01);
+  r.cy = f64_of(w0.s23);
+  r.cz = f64_of(w0.s45);
+  r.S = f64_of(w0.s67);
+  r.M32 = __builtin_bit_cast(float, w1.x);
+  r.next = (int)w1.y;
+  r.first = (int)w2.x;
+  r.count = (int)w2.y;
+  r.meta = (int)w3.x;
+  r.pad = 0;
+  r.M = f64_of(w4);
+  return r;
+}
+__device__ __forceinline__ ThetaNode load32(const ThetaNode* base, int c) {
+  const BH_CONST char* b = rec_at32(base, c);
+  const v8u_t w0 = *(const BH_CONST v8u_t*)b;             // cx, cy, cz, l
+  const v2u_t w1 = *(const BH_CONST v2u_t*)(b + 32);      // M32, next
+  const v2u_t w2 = *(const BH_CONST v2u_t*)(b + 40);      // first, count
+  const v2u_t w3 = *(const BH_CONST v2u_t*)(b + 48);      // s
+  const v2u_t w4 = *(const BH_CONST v2u_t*)(b + 56);      // meta, pad
+  ThetaNode r;
+  r.cx = f64_of(w0.s01);
+  r.cy = f64_of(w0.s23);
+  r.cz = f64_of(w0.s45);
+  r.l = f64_of(w0.s67);
+  r.M32 = __builtin_bit_cast(float, w1.x);
+  r.next = (int)w1.y;
+  r.first = (int)w2.x;
+  r.count = (int)w2.y;
+  r.s = f64_of(w3);
+  r.meta = (int)w4.x;
+  r.pad = 0;
+  return r;
+}
+static_assert(sizeof(WalkNode) == 64 && sizeof(ThetaNode) == 64, "load32 assumes 64-byte records");
+// Walk copies of n particles hold 2n + 1 records of 64 bytes: below 4 GiB for
+// n < 2^25.
+constexpr int kOff32MaxN = 1 << 25;
+
 template <bool kF64>
 struct StepNode<kF64, false> {
   const WalkNode* base;
   __device__ __forceinline__ WalkNode load(int c) const { return const_load(base, c); }
+  template <bool kOff32>
+  __device__ __forceinline__ WalkNode load_at(int c) const {
+    if constexpr (kOff32) return load32(base, c); else return const_load(base, c);
+  }
 };
 template <>
 struct StepNode<false, true> {
   const ThetaNode* base;
   __device__ __forceinline__ ThetaNode load(int c) const { return const_load(base, c); }
+  template <bool kOff32>
+  __device__ __forceinline__ ThetaNode load_at(int c) const {
+    if constexpr (kOff32) return load32(base, c); else return const_load(base, c);
+  }
 };
 template <>
 struct StepNode<true, true> {
   const Node* base;
   __device__ __forceinline__ Node load(int c) const { return const_load(base, c); }
+  template <bool kOff32>
+  __device__ __forceinline__ Node load_at(int c) const { return const_load(base, c); }
 };
 
 // Per-target state of a walk.
@@ -426,7 +494,7 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 // the node capacity, so a corrupted record can never send the cursor out of the
 // array, and every step moves the cursor forward or stays on a leaf for at most
 // its particle count.
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, bool kOff32>
 __device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
                                                  int end) {
   using Rec = decltype(wn.load(0));
@@ -437,13 +505,13 @@ __device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kF6
   const int last = 2 * a.n - 1;
   // (two steps per iteration, the records alternating between two sets of
   // registers, so that no step has to move the next record into place)
-  Rec ra = wn.load(C.c), rb;
+  Rec ra = wn.template load_at<kOff32>(C.c), rb;
   while (C.c < end) {
     walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(
-        a, C, ra, [&](int cn) { rb = wn.load(kRaw ? min(cn, last) : cn); });
+        a, C, ra, [&](int cn) { rb = wn.template load_at<kOff32>(kRaw ? min(cn, last) : cn); });
     if (C.c >= end) break;
     walk_step<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(
-        a, C, rb, [&](int cn) { ra = wn.load(kRaw ? min(cn, last) : cn); });
+        a, C, rb, [&](int cn) { ra = wn.template load_at<kOff32>(kRaw ? min(cn, last) : cn); });
   }
 }
 
@@ -478,6 +546,9 @@ template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bo
 __device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
                                               uint4 (*pf)[8], const int (&kc)[kT], int klo, int khi) {
   const int cap = 2 * a.n;
+  // (the plain nodes of the FP64 per-group-theta walk keep 64-bit addressing)
+  constexpr bool kRaw = kF64 && kPlain;
+  const bool off32 = !kRaw && a.n < kOff32MaxN;
   for (int k = klo; k <= khi; ++k) {
     const int r0 = min(max(uniform(a.croot[k]), 0), cap);
     const int r1 = min(max(uniform(a.croot[k + 1]), r0), cap);
@@ -488,8 +559,10 @@ __device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kF64, 
     if (r0 >= r1) continue;
     if constexpr (kLds)
       walk_loop_lds<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, wn, C, pf, r1);
+    else if (off32)
+      walk_loop_scalar<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket, true>(a, wn, C, r1);
     else
-      walk_loop_scalar<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, wn, C, r1);
+      walk_loop_scalar<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket, false>(a, wn, C, r1);
   }
 }
 

@@ -279,3 +279,19 @@ def test_full_size_sampled(bh, name, theta, tpl):
     say(f"  max err {e.max():.3e}  p99 {np.quantile(e, 0.99):.3e}  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
     assert e.max() <= F32_TOL
     assert pot_err(pot, w["pot"]).max() <= F32_TOL
+
+
+def test_walk_copy_above_4gib(bh):
+    """n = 2^25 + 4097 particles: the walk copy (2n + 1 records of 64 bytes) passes 4 GiB, so the walk
+    reads its records with 64-bit addresses instead of 32-bit offsets; sampled targets against the oracle."""
+    n = (1 << 25) + 4097
+    say(f"[full] uniform cube n={n} theta=0.6 (sampled targets): 64-bit record addressing")
+    rng = np.random.default_rng(7)
+    pos = rng.random((n, 3))
+    mass = np.full(n, 1.0 / n)
+    tg = inputs.sample_targets(n, 256, 17)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.6, 1e-3, targets=tg)
+    e = force_err(acc, w["acc"], w["amag"])
+    say(f"  max err {e.max():.3e}  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
+    assert e.max() <= F32_TOL
+    assert pot_err(pot, w["pot"]).max() <= F32_TOL
