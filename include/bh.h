@@ -220,11 +220,18 @@ BH_API int bh_autotune(bh_tree *t, double theta, double eps, void *acc, void *po
  * 1/sd[8]; the network sees bf16((x - mu) / sd). */
 
 /* Features of every Morton group g of t (Morton positions [64g, 64g+64); in a
- * forest the group's cluster sets N, L and the total mass): X [ceil(n/64)][8]
- * device FP32 = log2(h / (L (64/N)^(1/3) / 2)) with h the group's half-width,
- * n_g / 64, log10(M_g / (M n_g / N)), RMS mass radius / h, |centre of mass -
- * box centre| / h, log10 of the densities (M / l^3 over the mean) of the
- * smallest cell holding the group and of its parent, log2(its side / h). */
+ * forest the group's cluster sets N, L and the total mass M): X [ceil(n/64)][8]
+ * device FP32, scale-free, with h the half-width of the group's bounding box,
+ * c the smallest cell holding the group and l_c its side:
+ *   log2(h / (L (64/N)^(1/3) / 2)),
+ *   |group centre of mass - centre of mass of c| / l_c,
+ *   the same against the ancestor of c three levels up (or the root),
+ *   mass-weighted RMS radius about the group's centre of mass / h,
+ *   |centre of mass - box centre| / h,
+ *   log10 of the density M_c / l_c^3 of c over the mean M / L^3,
+ *   the same for the parent of c,
+ *   log2(l_c / h).
+ * Errors: BH_EINVAL for a null tree or X. */
 BH_API int bh_features(const bh_tree *t, float *X, void *stream);
 
 /* Per-group force error against a reference: for every Morton group g of t,
