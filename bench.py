@@ -203,10 +203,13 @@ def sweep_bench(args, bh, inputs):
 def learned_bench(args, bh, inputs):
     """Learned per-group opening parameter against fixed theta at equal accuracy (RMS relative
     force error 1e-3 against the FP64 direct sum on 65,536 sampled targets), on the clumpy field
-    N=8,388,608 (seed 4, eps 1e-4).  The network is trained on the GPU on 64 snapshots of
-    262,144 particles (seeds 100-163, Plummer and clumpy alternately); its shrink exponent is
-    picked on a held-out snapshot (seed 164).  Reported: interactions and walk time of the FP32
-    fixed-theta walk, the FP32 learned-theta walk, and the FP64 fixed-theta walk."""
+    N=8,388,608 (seed 4, eps 1e-4).  Two networks are trained on the GPU:
+    (a) on 64 snapshots of 262,144 particles (seeds 100-163, Plummer and clumpy alternately), its
+        shrink exponent picked on a held-out snapshot (seed 164);
+    (b) on labels from 2048 sampled groups of each of 8 clumpy fields at the evaluation's size
+        (N=8,388,608, seeds 200-207).
+    Reported: interactions and walk time of the FP32 fixed-theta walk, of the FP32 walks with
+    either network's theta, and of the FP64 fixed-theta walk."""
     from paper_1112_4539_amd import learn
     t0 = time.perf_counter()
     X, L = learn.build_dataset(range(100, 164), log=log)
@@ -214,17 +217,24 @@ def learned_bench(args, bh, inputs):
     net, hist = learn.train(X, L, epochs=60, log=log)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    log(f"[bench] labels {t1 - t0:.1f} s, training {t2 - t1:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    log(f"[bench] (a) labels {t1 - t0:.1f} s, training {t2 - t1:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    X8, L8 = learn.build_dataset_sampled(range(200, 208), 8388608, 2048, log=log)
+    t3 = time.perf_counter()
+    net8, hist8 = learn.train(X8, L8, epochs=80, batch=1024, log=log)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    log(f"[bench] (b) labels {t3 - t2:.1f} s, training {t4 - t3:.1f} s, loss {hist8[0]:.4f} -> {hist8[-1]:.4f}")
     target = learn.TARGET
 
-    def evaluate(pos, mass, eps, n_targets, seed, betas, with_fp64):
+    def evaluate(pos, mass, eps, n_targets, seed, nets, with_fp64):
+        """nets: {name: (network, [shrink exponents])}."""
         dev = torch.device("cuda:0")
         g32 = (torch.tensor(pos.astype(np.float32), device=dev), torch.tensor(mass.astype(np.float32), device=dev))
         n = len(pos)
         tg = torch.tensor(inputs.sample_targets(n, n_targets, seed), device=dev)
         a_ref, _ = bh.direct(g32[0].double(), g32[1].double(), eps, tg)
         T = bh.Tree(*g32)
-        raw = net.infer(T.features(), alpha=1.0, fallback=0.5)
+        X = T.features()
 
         def run(T, theta=None, tgrp=None, reps=3):
             st = T.walk_stats(theta if theta else 0.5, eps, theta_group=tgrp)
@@ -237,22 +247,21 @@ def learned_bench(args, bh, inputs):
             T.set_timing(False)
             return inter, min(ms)
 
-        def rms_fixed(T):
-            return lambda th: learn.rms_error(T.forces(th, eps)[0], a_ref, tg)
-
-        thf, ef = learn.bisect(rms_fixed(T), 0.1, 1.1, target)
+        thf, ef = learn.bisect(lambda th: learn.rms_error(T.forces(th, eps)[0], a_ref, tg), 0.1, 1.1, target)
         i_f, ms_f = run(T, theta=thf)
         out = {"fixed_fp32": dict(theta=thf, rms=ef, interactions=i_f, walk_ms=ms_f)}
-        for beta in betas:
-            def rms_l(alpha, beta=beta):
-                a, _ = T.forces(0.5, eps, theta_group=learn.scaled_theta(raw, alpha, beta))
-                return learn.rms_error(a, a_ref, tg)
-            al, el = learn.bisect(rms_l, 0.05, 4.0, target)
-            tgrp = learn.scaled_theta(raw, al, beta)
-            i_l, ms_l = run(T, tgrp=tgrp)
-            out[f"learned_beta{beta}"] = dict(alpha=al, beta=beta, rms=el, interactions=i_l, walk_ms=ms_l,
-                                              theta_mean=float(tgrp.mean()), interactions_vs_fixed=i_l / i_f,
-                                              walk_ms_vs_fixed=ms_l / ms_f)
+        for name, (nw, betas) in nets.items():
+            raw = nw.infer(X, alpha=1.0, fallback=0.5)
+            for beta in betas:
+                def rms_l(alpha, beta=beta):
+                    a, _ = T.forces(0.5, eps, theta_group=learn.scaled_theta(raw, alpha, beta))
+                    return learn.rms_error(a, a_ref, tg)
+                al, el = learn.bisect(rms_l, 0.05, 4.0, target)
+                tgrp = learn.scaled_theta(raw, al, beta)
+                i_l, ms_l = run(T, tgrp=tgrp)
+                out[f"{name}_beta{beta}"] = dict(alpha=al, beta=beta, rms=el, interactions=i_l, walk_ms=ms_l,
+                                                 theta_mean=float(tgrp.mean()), interactions_vs_fixed=i_l / i_f,
+                                                 walk_ms_vs_fixed=ms_l / ms_f)
         if with_fp64:
             T64 = bh.Tree(g32[0].double(), g32[1].double())
             th64, e64 = learn.bisect(lambda th: learn.rms_error(T64.forces(th, eps)[0], a_ref, tg), 0.1, 1.1, target)
@@ -261,22 +270,26 @@ def learned_bench(args, bh, inputs):
         return out
 
     pos, mass, eps = learn.training_snapshot(164)
-    held = evaluate(pos, mass, eps, 65536, 164, (1.0, 0.8, 0.6, 0.4), False)
+    held = evaluate(pos, mass, eps, 65536, 164, {"learned": (net, (1.0, 0.8, 0.6, 0.4))}, False)
     beta = min((v["interactions"], v["beta"]) for k, v in held.items() if k.startswith("learned"))[1]
     log(f"[bench] held-out snapshot: {json.dumps(held)}; shrink exponent {beta}")
     pos, mass, spec = inputs.make("clumpy8m")
-    res = evaluate(pos, mass, spec["eps"], args.samples, spec["seed"], (beta,), True)
+    res = evaluate(pos, mass, spec["eps"], args.samples, spec["seed"],
+                   {"learned": (net, (beta,)), "learned8m": (net8, (1.0,))}, True)
     log(f"[bench] clumpy 8M: {json.dumps(res)}")
     n = len(pos)
-    lr = res[f"learned_beta{beta}"]
+    lr = res["learned8m_beta1.0"]
     line = {"metric": "forces/s at RMS rel force err 1e-3, learned per-group theta (clumpy N=8M)",
             "value": n / (lr["walk_ms"] * 1e-3), "unit": "forces/s (walk)", "n_gpus": 1, "steps": 3,
             "warmup": 0, "ms_per_step": lr["walk_ms"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, eps={spec['eps']}; trained on 64 "
-                                   f"snapshots N=262144 (seeds 100-163)",
-                       "train_rows": int(L.shape[0]), "train_loss": [hist[0], hist[-1]],
-                       "label_s": t1 - t0, "train_s": t2 - t1, "shrink_exponent": beta, "heldout": held,
+            "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, eps={spec['eps']}; network trained "
+                                   f"on 2048 sampled groups of each of 8 clumpy fields N=8388608 (seeds 200-207)",
+                       "train_rows": int(L8.shape[0]), "train_loss": [hist8[0], hist8[-1]],
+                       "label_s": t3 - t2, "train_s": t4 - t3,
+                       "small_snapshot_network": {"train_rows": int(L.shape[0]), "train_loss": [hist[0], hist[-1]],
+                                                  "label_s": t1 - t0, "train_s": t2 - t1, "shrink_exponent": beta,
+                                                  "heldout": held},
                        "eval": res,
                        "forces_per_s": {k: n / (v["walk_ms"] * 1e-3) for k, v in res.items()}}}
     print(json.dumps(line), flush=True)

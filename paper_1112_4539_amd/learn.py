@@ -1,9 +1,10 @@
 """Learned opening parameter: labelling, training and use of the theta network.
 
-Host orchestration only: every number is computed by the library's kernels
+Host orchestration: the physics and the network run in the library's kernels
 (features, direct sum, force walks, per-group errors, the MLP's forward,
-gradient and Adam passes); this module chooses what to run.  The two pieces
-of host arithmetic are the feature normalisation constants (eight means and
+gradient and Adam passes); this module chooses what to run.  Host arithmetic
+is limited to the label allocation below (an argmin over the theta grid with
+a bisected multiplier), the feature normalisation constants (eight means and
 standard deviations of the training features) and the minibatch shuffles.
 
 Labels: a training snapshot is walked at every theta of the grid 0.20, 0.25,
@@ -15,7 +16,10 @@ lambda bisected so that the snapshot's overall RMS error is the target (1e-3)
 -- the least total cost at that error that per-group choices on the grid can
 reach.  (Labelling each group with the largest theta that keeps its own error
 within the target spends interactions where they buy little accuracy.)  The
-network is fitted to t = (theta* - 0.2) / 0.8 with the loss
+allocation can also be taken over a random sample of the groups of a large
+particle set (label_sampled): the direct sum then runs for the sampled groups'
+targets only, which makes labels affordable at the resolution the network is
+used at.  The network is fitted to t = (theta* - 0.2) / 0.8 with the loss
 mean((sigmoid(z) - t)^2).  At use, theta_g = min(alpha * theta(x_g),
 1.15), with alpha a single scale that the caller sets (e.g. by bisection to a
 global error target); a non-finite output falls back to a fixed theta.
@@ -92,6 +96,51 @@ def label_snapshot(pos, mass, eps, grid=THETA_GRID, target=TARGET):
     k = allocate(R, C, n_g, target)
     label = torch.tensor(np.asarray(grid, np.float32)[k], device="cuda")
     return X, label, R, C
+
+
+def label_sampled(pos, mass, eps, n_groups, seed, grid=THETA_GRID, target=TARGET):
+    """Features [S, 8] and labels [S] (device float32) of S = n_groups Morton groups sampled
+    (without replacement, from default_rng(seed); the last, possibly ragged group excluded) from one
+    particle set, plus their error and cost tables R, C [len(grid), S].  Labels as in
+    label_snapshot, the allocation taken over the sample: for large sets the direct sum then covers
+    only the sampled groups' 64 S targets."""
+    gp, gm = _dev(pos, torch.float32), _dev(mass, torch.float32)
+    T = bh.Tree(gp, gm)
+    X = T.features()
+    n, G = T.n, T.n_groups
+    n_groups = min(n_groups, G - 1)
+    gs = np.sort(np.random.default_rng(seed).choice(G - 1, n_groups, replace=False))
+    _, perm = T.export()
+    targets = np.asarray(perm, np.int64)[(gs[:, None] * 64 + np.arange(64)[None, :]).ravel()]
+    tg = torch.tensor(targets, device="cuda")
+    a_s, _ = bh.direct(gp.double(), gm.double(), eps, tg)
+    a_ref = torch.zeros((n, 3), dtype=torch.float64, device="cuda")  # groups outside the sample: unused
+    a_ref[tg] = a_s
+    gsel = torch.tensor(gs, device="cuda")
+    R, C = [], []
+    for th in grid:
+        st = T.walk_stats(th, eps)
+        R.append(T.group_error(st["acc"], a_ref)[gsel])
+        C.append(st["group_steps"].double()[gsel])
+    R = torch.stack(R).cpu().numpy()
+    C = torch.stack(C).cpu().numpy()
+    k = allocate(R, C, np.full(n_groups, 64.0), target)
+    label = torch.tensor(np.asarray(grid, np.float32)[k], device="cuda")
+    return X[gsel].contiguous(), label, R, C
+
+
+def build_dataset_sampled(seeds, n, n_groups, log=None):
+    """Training rows from clumpy fields of n particles (one per seed, eps 1e-4), n_groups sampled
+    groups each: labels at the resolution the network is to be used at."""
+    Xs, Ls = [], []
+    for s in seeds:
+        pos, mass = inputs.clumpy(n, s)
+        X, lab, _, _ = label_sampled(pos, mass, 1e-4, n_groups, s)
+        Xs.append(X)
+        Ls.append(lab)
+        if log:
+            log(f"[learn] snapshot seed={s} n={n} sampled groups={len(lab)} mean label={float(lab.mean()):.3f}")
+    return torch.cat(Xs), torch.cat(Ls)
 
 
 def training_snapshot(seed, n=262_144):
