@@ -17,9 +17,10 @@
 // from the compare), else to next(c).  Every target therefore meets exactly
 // the nodes of its own single-particle walk, in the same order, so lists and
 // summation order do not depend on how targets are grouped.  Node records are
-// wave-uniform and are read with scalar loads; there is no divergence in the
-// traversal itself.  In a forest a wave walks, in turn, the subtree of every
-// cluster its targets belong to.
+// wave-uniform and are read with scalar loads, the next one as soon as the
+// opening masks fix the cursor, so that its latency overlaps the terms; there
+// is no divergence in the traversal itself.  In a forest a wave walks, in
+// turn, the subtree of every cluster its targets belong to.
 //
 // Precision (FP32 variant): positions and masses are FP32.  The opening test
 // runs in FP64 on the FP64 centre of mass and the exactly widened position,
@@ -468,14 +469,14 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
   }
 }
 
-// Node records reach the walk through LDS.  The walk reads one record per
-// step and nearly every record misses the small scalar cache, whose miss
-// handling then sets the pace; the vector path has the throughput but a
-// longer latency.  So each step copies both possible successors of the
+// A second route for node records, a launch option (a share of the waves
+// takes it): through LDS.  Each step copies both possible successors of the
 // current node (c+1 and next(c)) with the LDS-DMA load (global_load_lds_dwordx4:
 // lanes 0-3 bring the four 16-byte quarters of one record, lanes 4-7 those
 // of the other) into the wave's spare buffer, and the next step reads the one
 // it needs with broadcast LDS reads.  The copy's latency overlaps one step.
+// On the measured workloads the scalar route with its look-ahead load is the
+// faster one.
 typedef __attribute__((address_space(3))) void lds_void;
 
 template <typename Rec>
