@@ -702,8 +702,15 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 // next group from a device counter until none is left, so the load balances
 // itself and no workgroup waits for a dispatch slot.  Every wave leaves once
 // the counter passes the last group.
+// The group loop keeps the launch arguments in scalar registers; left alone
+// the compiler takes 106 of them, which caps the kernel at 7 waves per SIMD
+// (the plain form runs 8).  The FP32 uniform-theta force kernels of one target
+// per lane are asked for 8 waves: their spare scalars then go to VGPR lanes
+// outside the step loop.  (The others would spill vector registers to memory.)
 template <bool kF64, int kT, int kMode, bool kSoft, bool kGroupTheta>
-__global__ __launch_bounds__(256) void k_walk_persistent(WalkArgs a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(!kF64 && kT == 1 && kMode == kWalkForces && !kGroupTheta ? 8 : 1)))
+void k_walk_persistent(WalkArgs a) {
   __shared__ uint4 pf_lds[4][2][8];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
