@@ -115,7 +115,8 @@ size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_
   t.nexcl = reinterpret_cast<int32_t*>(take(4 * (N + 1)));
   t.lmask = reinterpret_cast<uint32_t*>(take(4 * (N + 1)));
   t.nodes = reinterpret_cast<bh::Node*>(take(sizeof(bh::Node) * nodes));
-  t.Mx = reinterpret_cast<double*>(take(24 * nodes));
+  t.mom = reinterpret_cast<bh::Mom*>(take(sizeof(bh::Mom) * nodes));
+  t.nx = reinterpret_cast<int32_t*>(take(4 * nodes));
   // (one spare record past the last: the walk reads the record after its
   // cursor's last position before it tests the loop bound)
   t.wnodes = reinterpret_cast<bh::WalkNode*>(take(sizeof(bh::WalkNode) * (nodes + 1)));

@@ -659,7 +659,7 @@ __global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict
                                                         const uint32_t* __restrict__ lmask,
                                                         const int32_t* __restrict__ ustart,
                                                         int32_t* __restrict__ ipre, Node* __restrict__ nodes,
-                                                        int nmax) {
+                                                        int32_t* __restrict__ nx, int nmax) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nmax || v >= cnt->n_internal) return;
   const int s = ilevel[v], f = ifirst[v], l = ilast[v];
@@ -676,6 +676,7 @@ __global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict
   nd.count = ustart[l + 1] - ustart[f];
   nd.meta = s << 8;
   nodes[pre] = nd;
+  nx[pre] = nd.next;
 }
 
 template <typename T4>
@@ -685,7 +686,8 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
                                                     const int32_t* __restrict__ nstart,
                                                     const int32_t* __restrict__ nexcl,
                                                     const int32_t* __restrict__ ustart, const T4* __restrict__ ps,
-                                                    Node* __restrict__ nodes, double* __restrict__ Mx, int nmax) {
+                                                    Node* __restrict__ nodes, Mom* __restrict__ mom,
+                                                    int32_t* __restrict__ nx, int nmax) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int U = cnt->n_unique;
   if (x >= nmax || x >= U) return;
@@ -745,34 +747,37 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
   nd.count = count;
   nd.meta = 1 | (count > 1 ? 2 : 0) | (level << 8);
   nodes[pre] = nd;
-  Mx[3 * (int64_t)pre] = X;
-  Mx[3 * (int64_t)pre + 1] = Y;
-  Mx[3 * (int64_t)pre + 2] = Z;
+  mom[pre] = Mom{M, X, Y, Z};
+  nx[pre] = pre + 1;
 }
 
 // Moments of the internal nodes of one level (children are deeper, so they are
 // final).  Children are pre+1, next(pre+1), ... < next(pre), in octant order.
+// The chain and the sums read the compact next array and the 32-byte moment
+// records rather than the 64-byte nodes.
 __global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict__ cnt, const Cube* __restrict__ cubes,
                                                        const int32_t* __restrict__ ucid,
                                                        const int32_t* __restrict__ ilevel,
                                                        const int32_t* __restrict__ ifirst,
                                                        const int32_t* __restrict__ ipre,
                                                        const uint64_t* __restrict__ ukey, Node* __restrict__ nodes,
-                                                       double* __restrict__ Mx, int level, int nmax) {
+                                                       Mom* __restrict__ mom, const int32_t* __restrict__ nx,
+                                                       int level, int nmax) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nmax || v >= cnt->n_internal || ilevel[v] != level) return;
   const int p = ipre[v];
   const Cube* cube = cubes + (ucid ? ucid[ifirst[v]] : 0);
   const int n_nodes = cnt->n_nodes;
-  const int end = min(nodes[p].next, n_nodes);
+  const int end = min(nx[p], n_nodes);
   double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
   // at most 8 children; the bound also keeps a corrupted record from looping
   int c = p + 1;
-  for (int k = 0; k < 8 && c < end; ++k, c = max(nodes[c].next, c + 1)) {
-    M += nodes[c].M;
-    X += Mx[3 * (int64_t)c];
-    Y += Mx[3 * (int64_t)c + 1];
-    Z += Mx[3 * (int64_t)c + 2];
+  for (int k = 0; k < 8 && c < end; ++k, c = max(nx[c], c + 1)) {
+    const Mom q = mom[c];
+    M += q.M;
+    X += q.X;
+    Y += q.Y;
+    Z += q.Z;
   }
   const double l = nodes[p].l;
   const uint64_t prefix = (level == 0) ? 0ull : (ukey[ifirst[v]] >> (63 - 3 * level));
@@ -795,9 +800,7 @@ __global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict_
   nodes[p].cz = com[2];
   nodes[p].M = M;
   nodes[p].s = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-  Mx[3 * (int64_t)p] = X;
-  Mx[3 * (int64_t)p + 1] = Y;
-  Mx[3 * (int64_t)p + 2] = Z;
+  mom[p] = Mom{M, X, Y, Z};
 }
 
 // ---------------------------------------------------------------- driver
@@ -866,12 +869,12 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
   if ((e = scan_excl(w.nstart, w.nexcl, n + 1, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
   k_croot_final<<<nblk(K + 1, 256), 256, 0, st>>>(K, w.nexcl, w.croot);
   k_nodes_internal<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.ilevel, w.ifirst, w.ilast,
-                                                     w.nstart, w.nexcl, w.lmask, w.ustart, w.ipre, w.nodes, n);
+                                                     w.nstart, w.nexcl, w.lmask, w.ustart, w.ipre, w.nodes, w.nx, n);
   k_nodes_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.split, w.nstart, w.nexcl, w.ustart,
-                                                 reinterpret_cast<const T4*>(w.ps), w.nodes, w.Mx, n);
+                                                 reinterpret_cast<const T4*>(w.ps), w.nodes, w.mom, w.nx, n);
   for (int level = kLevels - 1; level >= 0; --level)
     k_moments_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.ilevel, w.ifirst, w.ipre, w.ukey,
-                                                  w.nodes, w.Mx, level, n);
+                                                  w.nodes, w.mom, w.nx, level, n);
   return hipGetLastError();
 }
 

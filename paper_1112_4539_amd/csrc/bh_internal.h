@@ -14,6 +14,12 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kBboxBlocks = 1024;
 
+// Mass and first moments (sum of m x) of a node, FP64: what a parent's moment
+// pass reads of each child, in one aligned 32-byte record.
+struct alignas(32) Mom {
+  double M, X, Y, Z;
+};
+
 // Views into the caller's workspace used by one build.  A build covers K >= 1
 // independent clusters (a forest): cluster k is the caller's particles
 // [off[k], off[k+1]) and gets its own root cube, keys and tree.  The sort puts
@@ -45,7 +51,8 @@ struct BuildWs {
   int32_t *nstart, *nexcl;  // [n + 1]
   uint32_t* lmask;          // [n + 1]
   Node* nodes;              // [2n]
-  double* Mx;               // [2n][3]
+  Mom* mom;                 // [2n] mass and first moments of every node, for the moment passes
+  int32_t* nx;              // [2n] next(c) of every node, for the moment passes
   WalkNode* wnodes;         // [2n] walk copy of the nodes for the last uniform theta
 };
 
