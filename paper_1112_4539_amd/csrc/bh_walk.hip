@@ -360,8 +360,9 @@ __device__ __forceinline__ void bucket_step(const WalkArgs& a, Cursor<kF64, kT>&
 template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, typename Rec,
           typename Fetch>
 __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C, const Rec& rec, Fetch&& fetch) {
-  // The record was read from LDS by every lane; its integer fields steer the
-  // wave's control flow, so take them as wave-uniform values.
+  // On the LDS route the record was read by every lane; its integer fields
+  // steer the wave's control flow, so take them as wave-uniform values (on the
+  // scalar route they already are, and this costs nothing).
   Rec cur = rec;
   cur.next = uniform(rec.next);
   cur.first = uniform(rec.first);
