@@ -230,8 +230,10 @@ __global__ void k_single_off(int64_t* __restrict__ off, int64_t n) {
 
 __device__ __forceinline__ int64_t clamp_off(int64_t v, int64_t n) { return v < 0 ? 0 : (v > n ? n : v); }
 
-// Cluster of caller index i: the k with off[k] <= i < off[k+1].
-__device__ __forceinline__ int seg_of(const int64_t* __restrict__ off, int K, int64_t i) {
+// Cluster of caller index i: the k with off[k] <= i < off[k+1] (off in global
+// memory or in an LDS copy).
+template <typename P>
+__device__ __forceinline__ int seg_of(P off, int K, int64_t i) {
   int lo = 0, hi = K;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
@@ -327,27 +329,47 @@ __global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, int n, 
 }
 
 // ---------------------------------------------------------------- radix sort
-// Digit of item i of a pass: 8 bits of its key, or (kSeg) 8 bits of its
-// cluster, looked up through its caller index.
-template <bool kSeg>
-__device__ __forceinline__ uint32_t digit_of(uint64_t key, int32_t val, const int32_t* __restrict__ seg, int shift) {
-  if constexpr (kSeg) return ((uint32_t)seg[val] >> shift) & 255u;
-  return (uint32_t)(key >> shift) & 255u;
-}
+// Digit sources of a pass: 8 bits of the key, or 8 bits of the item's cluster.
+// The cluster of caller index v is a search over the cluster offsets, staged in
+// LDS when they fit (the offsets are sorted and caller order keeps each cluster
+// contiguous), else the per-index cluster array, which the key passes leave in
+// no useful order, so that lookup is a scattered read.
+enum SortDigit { kDigKey = 0, kDigSegLds = 1, kDigSegIdx = 2 };
+constexpr int kSegLds = 2048;  // most cluster offsets (K + 1) staged in LDS
 
-template <bool kSeg>
+template <int kDig>
+struct SegTable {
+  // off[0..K] when the offsets sit in LDS
+  int64_t off[kDig == kDigSegLds ? kSegLds : 1];
+  __device__ __forceinline__ void load(const int64_t* __restrict__ g, int K) {
+    if constexpr (kDig == kDigSegLds) {
+      for (int k = threadIdx.x; k <= K; k += blockDim.x) off[k] = g[k];
+    }
+  }
+  __device__ __forceinline__ uint32_t digit(uint64_t key, int32_t val, const int32_t* __restrict__ seg, int K,
+                                            int shift) const {
+    if constexpr (kDig == kDigKey) return (uint32_t)(key >> shift) & 255u;
+    if constexpr (kDig == kDigSegLds) return ((uint32_t)seg_of(off, K, val) >> shift) & 255u;
+    return ((uint32_t)seg[val] >> shift) & 255u;
+  }
+};
+
+template <int kDig>
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __restrict__ keys,
                                                           const int32_t* __restrict__ vals,
-                                                          const int32_t* __restrict__ seg, int n, int shift,
-                                                          int32_t* __restrict__ hist, int ntiles) {
+                                                          const int32_t* __restrict__ seg,
+                                                          const int64_t* __restrict__ seg_off, int K, int n,
+                                                          int shift, int32_t* __restrict__ hist, int ntiles) {
   __shared__ uint32_t h[256];
+  __shared__ SegTable<kDig> tab;
   h[threadIdx.x] = 0;
+  tab.load(seg_off, K);
   __syncthreads();
   int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
   for (int r = 0; r < kSortItems; ++r) {
     int64_t i = base + r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[digit_of<kSeg>(kSeg ? 0ull : keys[i], kSeg ? vals[i] : 0, seg, shift)], 1u);
+    if (i < n) atomicAdd(&h[tab.digit(kDig == kDigKey ? keys[i] : 0ull, kDig == kDigKey ? 0 : vals[i], seg, K, shift)], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = (int32_t)h[threadIdx.x];
@@ -360,10 +382,11 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint64_t* __rest
 // placed in LDS sorted by digit, and the tile then leaves in that order, so
 // that consecutive lanes write consecutive addresses of one digit's run
 // instead of 8- and 4-byte pieces all over the output.
-template <bool kSeg>
+template <int kDig>
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                              const int32_t* __restrict__ vin,
                                                              const int32_t* __restrict__ seg,
+                                                             const int64_t* __restrict__ seg_off, int K,
                                                              uint64_t* __restrict__ kout,
                                                              int32_t* __restrict__ vout, int n, int shift,
                                                              const int32_t* __restrict__ offs, int ntiles) {
@@ -376,19 +399,21 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __r
   __shared__ uint32_t loff[256];          // tile position of the first item of each digit
   __shared__ uint32_t wslot[kWaves][256]; // per wave: its counts, then its next slot per digit
   __shared__ uint32_t wsum[kWaves];
+  __shared__ SegTable<kDig> tab;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
   const int m = (int)min((int64_t)kSortTile, (int64_t)n - tile0);  // items in this tile
   goff[t] = (uint32_t)offs[(int64_t)t * ntiles + blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kWaves; ++k) wslot[k][t] = 0;
+  tab.load(seg_off, K);
   __syncthreads();
   // per-wave digit counts
   for (int r = 0; r < kPerWave / 64; ++r) {
     const int j = w * kPerWave + r * 64 + lane;
     if (j < m) {
       const int64_t i = tile0 + j;
-      atomicAdd(&wslot[w][digit_of<kSeg>(kSeg ? 0ull : kin[i], kSeg ? vin[i] : 0, seg, shift)], 1u);
+      atomicAdd(&wslot[w][tab.digit(kDig == kDigKey ? kin[i] : 0ull, kDig == kDigKey ? 0 : vin[i], seg, K, shift)], 1u);
     }
   }
   __syncthreads();
@@ -430,7 +455,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint64_t* __r
     const int64_t i = tile0 + j;
     const uint64_t key = valid ? kin[i] : 0ull;
     const int32_t val = valid ? vin[i] : 0;
-    const uint32_t d = valid ? digit_of<kSeg>(key, val, seg, shift) : 0u;
+    const uint32_t d = valid ? tab.digit(key, val, seg, K, shift) : 0u;
     uint64_t peers = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -835,18 +860,26 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
   for (unsigned r = (unsigned)(K - 1); r; r >>= 8) ++seg_passes;
   uint64_t *kin = w.key_a, *kout = w.key_b;
   int32_t *vin = w.idx_a, *vout = w.idx_b;
+  const bool seg_lds = K + 1 <= kSegLds;
   for (int pass = 0; pass < 8 + seg_passes; ++pass) {
     const bool segp = pass >= 8;
     const int shift = segp ? 8 * (pass - 8) : 8 * pass;
-    if (segp)
-      k_rs_hist<true><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, n, shift, w.hist, ntiles);
+    if (!segp)
+      k_rs_hist<kDigKey><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, w.seg_off, K, n, shift, w.hist, ntiles);
+    else if (seg_lds)
+      k_rs_hist<kDigSegLds><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, w.seg_off, K, n, shift, w.hist, ntiles);
     else
-      k_rs_hist<false><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, n, shift, w.hist, ntiles);
+      k_rs_hist<kDigSegIdx><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, w.seg_off, K, n, shift, w.hist, ntiles);
     if ((e = scan_excl(w.hist, w.hist, 256 * ntiles, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
-    if (segp)
-      k_rs_scatter<true><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, kout, vout, n, shift, w.hist, ntiles);
+    if (!segp)
+      k_rs_scatter<kDigKey><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, w.seg_off, K, kout, vout, n, shift,
+                                                             w.hist, ntiles);
+    else if (seg_lds)
+      k_rs_scatter<kDigSegLds><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, w.seg_off, K, kout, vout, n, shift,
+                                                                w.hist, ntiles);
     else
-      k_rs_scatter<false><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, kout, vout, n, shift, w.hist, ntiles);
+      k_rs_scatter<kDigSegIdx><<<ntiles, kSortThreads, 0, st>>>(kin, vin, w.seg, w.seg_off, K, kout, vout, n, shift,
+                                                                w.hist, ntiles);
     uint64_t* tk = kin; kin = kout; kout = tk;
     int32_t* tv = vin; vin = vout; vout = tv;
   }

@@ -132,6 +132,34 @@ def test_forest_against_oracle(bh, prec):
         assert pot_err(pot, w["pot"]).max() <= tol, k
 
 
+@pytest.mark.parametrize("K", [300, 2047, 2048, 3001])
+def test_forest_many_clusters(bh, K):
+    """Cluster counts around the sort's two ways of finding an item's cluster:
+    a search over the offsets staged in LDS (K + 1 <= 2048) and the per-index
+    cluster array above that; both need two cluster digits."""
+    say(f"[forest] {K} small clusters fp32")
+    rng = np.random.default_rng(K)
+    sizes = rng.integers(0, 48, K)
+    sizes[rng.choice(K, K // 10, replace=False)] = 0
+    sizes[-1] = 5
+    off = np.zeros(K + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    ctr = rng.normal(size=(K, 3)) * 10.0
+    pos = rng.normal(size=(n, 3)) * 0.1 + np.repeat(ctr, sizes, axis=0)
+    mass = rng.random(n) + 0.5
+    picks = sorted(set(rng.choice(K, 12, replace=False).tolist()) | {0, 255, 256, K - 1})
+    F, st = _forest_vs_alone(bh, pos, mass, off, "fp32", 0.6, 0.01, clusters=picks)
+    roots = F.roots().cpu().numpy()
+    # every cluster's subtree holds exactly its own particles
+    rec = F.export()[0]
+    for k in range(K):
+        if sizes[k]:
+            assert rec[roots[k]]["count"] == sizes[k] and rec[roots[k]]["first"] == off[k], k
+        else:
+            assert roots[k] == roots[k + 1], k
+
+
 def test_forest_bad_offsets_reported(bh):
     say("[forest] invalid offsets")
     pos = torch.rand((100, 3), device="cuda")
