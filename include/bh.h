@@ -142,7 +142,12 @@ BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *st
 /* Launch shape of the walk: waves_per_block in {1, 2, 4}; xcd_chunk >= 0
  * (runs of workgroups kept on one XCD; 0 = plain order).  target_order 0 =
  * Morton order (groups of Morton-consecutive targets), 1 = caller order (the
- * paper's unsorted experiment, Sec. 5).  lds_share in [0, 64]: how many waves
+ * paper's unsorted experiment, Sec. 5), 2 = Hilbert order (the default):
+ * targets sorted by cluster and the Hilbert index of their cell ten levels
+ * below the cluster's root cube (fewer in a forest), ties in Morton order, so
+ * that a group is a face-connected run of cells; the first walk after each
+ * build forms this order with a 4-pass radix sort in the workspace (5 passes
+ * beyond 131,072 clusters).  lds_share in [0, 64]: how many waves
  * out of 64 read node records through LDS copies instead of the scalar cache.
  * persistent 0 = one wavefront per group of 64 targets, 1 = a grid that fits
  * the chip at once whose wavefronts take groups from a device counter (kept in

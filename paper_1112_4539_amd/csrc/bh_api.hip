@@ -27,7 +27,8 @@ struct bh_tree {
   int32_t* queue = nullptr; // group counter of the persistent walk
   int waves_per_block = 1;
   int xcd_chunk = 0;
-  int target_order = 0;
+  int target_order = 2;
+  mutable bool horder_ready = false;  // w.horder holds the Hilbert order of the current build
   int lds_share64 = 0;
   int persistent = 0;
   int targets_per_lane = 1;
@@ -120,6 +121,7 @@ size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_
   // (one spare record past the last: the walk reads the record after its
   // cursor's last position before it tests the loop bound)
   t.wnodes = reinterpret_cast<bh::WalkNode*>(take(sizeof(bh::WalkNode) * (nodes + 1)));
+  t.horder = reinterpret_cast<int32_t*>(take(4 * N));
   int32_t* r = reinterpret_cast<int32_t*>(take(4 * N));
   if (w) *w = t;
   if (rank) *rank = r;
@@ -146,6 +148,7 @@ int sync_counts(const bh_tree* t, hipStream_t st, bh::Counts* c) {
 
 hipError_t enqueue_build(const bh_tree* t, hipStream_t st) {
   const int n = (int)t->n;
+  t->horder_ready = false;
   hipError_t e = t->prec == BH_FP64
                      ? bh::build_tree_f64(static_cast<const double*>(t->pos), static_cast<const double*>(t->mass), n,
                                           t->w, st)
@@ -181,6 +184,12 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
                                          reinterpret_cast<bh::ThetaNode*>(t->w.wnodes), st);
     if (e != hipSuccess) return hip_fail(e, "launching the per-group walk copy");
   }
+  if (t->target_order == 2 && !t->horder_ready) {
+    // (once per build; a graph that captures the build captures this too)
+    hipError_t e = bh::hilbert_order(t->prec == BH_FP64, (int)t->n, t->w, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the Hilbert target order");
+    t->horder_ready = true;
+  }
   bh::WalkArgs a{};
   a.nodes = t->w.nodes;
   a.cnt = t->w.counts;
@@ -188,7 +197,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.tnodes = reinterpret_cast<const bh::ThetaNode*>(t->w.wnodes);
   a.ps = t->w.ps;
   a.perm = t->w.idx_a;
-  a.order = t->target_order == 1 ? t->rank : nullptr;
+  a.order = t->target_order == 1 ? t->rank : t->target_order == 2 ? t->w.horder : nullptr;
   a.scid = t->n_seg > 1 ? t->w.scid : nullptr;  // (a single tree keeps no cluster ids)
   a.croot = t->w.croot;
   a.seg_off = t->w.seg_off;
@@ -353,7 +362,7 @@ int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int targe
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(BH_EINVAL, "waves_per_block must be 1, 2 or 4");
   if (xcd_chunk < 0) return fail(BH_EINVAL, "xcd_chunk must be >= 0");
-  if (target_order != 0 && target_order != 1) return fail(BH_EINVAL, "target_order must be 0 or 1");
+  if (target_order < 0 || target_order > 2) return fail(BH_EINVAL, "target_order must be 0, 1 or 2");
   if (lds_share < 0 || lds_share > 64) return fail(BH_EINVAL, "lds_share must be in [0, 64]");
   if (persistent != 0 && persistent != 1) return fail(BH_EINVAL, "persistent must be 0 or 1");
   if (targets_per_lane != 1 && targets_per_lane != 2) return fail(BH_EINVAL, "targets_per_lane must be 1 or 2");
@@ -443,6 +452,9 @@ int bh_graph_create(bh_tree* t, double theta, double eps, void* acc, void* pot, 
                                : BH_OK;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
+    // nothing captured has run: an eager walk before the first replay must
+    // form the Hilbert order itself
+    t->horder_ready = false;
     if (eb != hipSuccess) e = eb;
     if (e == hipSuccess && wrc != BH_OK) {
       if (graph) (void)hipGraphDestroy(graph);

@@ -926,6 +926,114 @@ hipError_t make_rank(const int32_t* perm, int n, int32_t* rank, hipStream_t st) 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- Hilbert walk order
+// The walk's targets go in groups of 64 consecutive positions of an order.  In
+// Morton order a group that straddles the edge of a large cell is split between
+// distant cells, which widens the group's union walk; in Hilbert order a group
+// is a face-connected run of cells.  Only the coarse levels matter (measured:
+// 10 levels give the full-depth order's walk on a clumpy 4M field), so the
+// order sorts Morton positions by (cluster, Hilbert index of the cell
+// hilbert_levels(K) below the cluster's root cube), ties in Morton order, in as
+// few 8-bit passes as the key needs.
+
+// Hilbert index of the cell (x, y, z) of a 2^b grid, by Skilling's transform
+// ("Programming the Hilbert curve", AIP Conf. Proc. 707, 2004): undo the
+// excess work of the Gray-code walk level by level, Gray-encode, then
+// interleave with x as the most significant bit of each triplet.
+__device__ __forceinline__ uint32_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int b) {
+  uint32_t X[3] = {x, y, z};
+  const uint32_t top = 1u << (b - 1);
+  for (uint32_t q = top; q > 1; q >>= 1) {
+    const uint32_t low = q - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & q) {
+        X[0] ^= low;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & low;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t q = top; q > 1; q >>= 1)
+    if (X[2] & q) t ^= q - 1;
+  uint32_t h = 0;
+  for (int j = b - 1; j >= 0; --j)
+    h = (h << 3) | ((((X[0] ^ t) >> j) & 1u) << 2) | ((((X[1] ^ t) >> j) & 1u) << 1) | (((X[2] ^ t) >> j) & 1u);
+  return h;
+}
+
+static int bits_of(unsigned v) {
+  int b = 0;
+  for (; v; v >>= 1) ++b;
+  return b;
+}
+
+// Levels of the Hilbert cells: 10 for a single tree (four passes; 8 levels in
+// three passes walked 2 % slower), fewer in a forest so that the cluster id and
+// the index share 32 bits where they can.
+static int hilbert_levels(int K) {
+  const int cbits = bits_of((unsigned)(K - 1));
+  return max(5, min(10, (32 - cbits) / 3));
+}
+
+// Sort key of Morton position k: its cluster above the Hilbert index of its
+// particle's cell `levels` below the cluster's root cube (the grid coordinates
+// are those of the Morton keys).
+template <typename T4>
+__global__ __launch_bounds__(256) void k_hkeys(const T4* __restrict__ ps, int n, const Cube* __restrict__ cubes,
+                                               const int32_t* __restrict__ scid, int levels,
+                                               uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int cl = scid ? scid[k] : 0;
+  const Cube* cube = cubes + cl;
+  const T4 p = ps[k];
+  const double c[3] = {(double)p.x, (double)p.y, (double)p.z};
+  uint32_t q[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double t = floor((c[d] - cube->lo[d]) * cube->scale);
+    if (!(t >= 0.0)) t = 0.0;
+    if (t > (double)(kGrid - 1)) t = (double)(kGrid - 1);
+    q[d] = (uint32_t)t >> (kLevels - levels);
+  }
+  keys[k] = ((uint64_t)(uint32_t)cl << (3 * levels)) | hilbert3(q[0], q[1], q[2], levels);
+  idx[k] = k;
+}
+
+template <typename T4>
+static hipError_t hilbert_impl(int n, const BuildWs& w, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int K = w.n_seg;
+  const int levels = hilbert_levels(K);
+  const int passes = (3 * levels + bits_of((unsigned)(K - 1)) + 7) / 8;
+  k_hkeys<T4><<<nblk(n, 256), 256, 0, st>>>(reinterpret_cast<const T4*>(w.ps), n, w.cube, K > 1 ? w.scid : nullptr,
+                                            levels, w.key_a, w.horder);
+  const int ntiles = (n + kSortTile - 1) / kSortTile;
+  uint64_t *kin = w.key_a, *kout = w.key_b;
+  int32_t *vin = w.horder, *vout = w.idx_b;
+  hipError_t e;
+  for (int pass = 0; pass < passes; ++pass) {
+    k_rs_hist<kDigKey><<<ntiles, kSortThreads, 0, st>>>(kin, vin, nullptr, w.seg_off, K, n, 8 * pass, w.hist, ntiles);
+    if ((e = scan_excl(w.hist, w.hist, 256 * ntiles, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
+    k_rs_scatter<kDigKey><<<ntiles, kSortThreads, 0, st>>>(kin, vin, nullptr, w.seg_off, K, kout, vout, n, 8 * pass,
+                                                           w.hist, ntiles);
+    uint64_t* tk = kin; kin = kout; kout = tk;
+    int32_t* tv = vin; vin = vout; vout = tv;
+  }
+  if (vin != w.horder) k_copy_kv<<<nblk(n, 256), 256, 0, st>>>(kin, vin, kout, w.horder, n);
+  return hipGetLastError();
+}
+
+hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st) {
+  return f64 ? hilbert_impl<double4>(n, w, st) : hilbert_impl<float4>(n, w, st);
+}
+
 hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st) {
   return build_impl<float, float4>(pos, mass, n, w, st);
 }

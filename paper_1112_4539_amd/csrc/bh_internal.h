@@ -54,12 +54,18 @@ struct BuildWs {
   Mom* mom;                 // [2n] mass and first moments of every node, for the moment passes
   int32_t* nx;              // [2n] next(c) of every node, for the moment passes
   WalkNode* wnodes;         // [2n] walk copy of the nodes for the last uniform theta
+  int32_t* horder;          // [n] Morton positions in the Hilbert walk order (filled on demand)
 };
 
 hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total, hipStream_t st);
 hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st);
 hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, hipStream_t st);
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+// Walk order of the targets (w.horder): Morton positions sorted by cluster and
+// the Hilbert index of their cell a few levels below the cluster's root cube.
+// Uses the sort buffers of the build, so it runs after it; w.key_a, w.key_b
+// and w.idx_b are overwritten.
+hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st);
 
 // Tree walk launch.  Targets are processed in groups of 64 (one wavefront);
 // group g holds the targets at positions [64g, 64g+64) of `order` (Morton

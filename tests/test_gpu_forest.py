@@ -132,14 +132,15 @@ def test_forest_against_oracle(bh, prec):
         assert pot_err(pot, w["pot"]).max() <= tol, k
 
 
-@pytest.mark.parametrize("K", [300, 2047, 2048, 3001])
-def test_forest_many_clusters(bh, K):
+@pytest.mark.parametrize("K,smax", [(300, 48), (2047, 48), (2048, 48), (3001, 48), (140_000, 4)])
+def test_forest_many_clusters(bh, K, smax):
     """Cluster counts around the sort's two ways of finding an item's cluster:
     a search over the offsets staged in LDS (K + 1 <= 2048) and the per-index
-    cluster array above that; both need two cluster digits."""
+    cluster array above that; both need two cluster digits.  Beyond 131,072
+    clusters the Hilbert target order's key needs an odd number of passes."""
     say(f"[forest] {K} small clusters fp32")
     rng = np.random.default_rng(K)
-    sizes = rng.integers(0, 48, K)
+    sizes = rng.integers(0, smax, K)
     sizes[rng.choice(K, K // 10, replace=False)] = 0
     sizes[-1] = 5
     off = np.zeros(K + 1, np.int64)
@@ -201,9 +202,9 @@ def test_forest_full_size(bh):
         assert torch.equal(a1, a0) and torch.equal(p1, p0)
 
 
-@pytest.mark.parametrize("forest", [False, True])
-def test_graph_replays_match_eager(bh, forest):
-    say(f"[graph] replays forest={forest}")
+@pytest.mark.parametrize("forest,order", [(False, 0), (True, 0), (False, 2), (True, 2)])
+def test_graph_replays_match_eager(bh, forest, order):
+    say(f"[graph] replays forest={forest} target order {order}")
     if forest:
         pos, mass, off = inputs.clusters(24, 11, nmin=64, nmax=4096)
     else:
@@ -213,10 +214,16 @@ def test_graph_replays_match_eager(bh, forest):
     gm = torch.tensor(mass, dtype=torch.float32, device="cuda")
     go = None if off is None else torch.tensor(off, device="cuda")
     T = bh.Tree(gp, gm, offsets=go)
-    T.set_walk_config(2, 0, 0, 16, 1, 2)
+    T.set_walk_config(2, 0, order, 16, 1, 2)
     acc = torch.zeros((len(pos), 3), dtype=torch.float32, device="cuda")
     pot = torch.zeros((len(pos),), dtype=torch.float32, device="cuda")
     G = T.graph(0.5, 0.01, acc, pot)
+    # an eager walk between the capture and the first replay
+    a0, p0 = T.forces(0.5, 0.01)
+    E0 = bh.Tree(gp.clone(), gm.clone(), offsets=go)
+    a0e, p0e = E0.forces(0.5, 0.01)
+    torch.cuda.synchronize()
+    assert torch.equal(a0, a0e) and torch.equal(p0, p0e)
     rng = np.random.default_rng(5)
     for rep in range(4):
         # new contents in the same input tensors, then one replay

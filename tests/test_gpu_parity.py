@@ -216,7 +216,7 @@ def test_launch_shapes_and_target_order_bitexact(bh):
     ref = T.forces(0.5, 1e-4)
     for wpb in (1, 2, 4):
         for chunk in (0, 4, 16):
-            for order in (0, 1):
+            for order in (0, 1, 2):
                 for share in (0, 24, 64):
                     for pers in (0, 1):
                         for tpl in (1, 2):
