@@ -239,6 +239,7 @@ def learned_bench(args, bh, inputs):
         tg = torch.tensor(inputs.sample_targets(n, n_targets, seed), device=dev)
         a_ref, _ = bh.direct(g32[0].double(), g32[1].double(), eps, tg)
         T = bh.Tree(*g32)
+        T.set_walk_config(target_order=args.target_order)
         X = T.features()
 
         def run(T, theta=None, tgrp=None, reps=3):
@@ -269,6 +270,7 @@ def learned_bench(args, bh, inputs):
                                                  walk_ms_vs_fixed=ms_l / ms_f)
         if with_fp64:
             T64 = bh.Tree(g32[0].double(), g32[1].double())
+            T64.set_walk_config(target_order=args.target_order)
             th64, e64 = learn.bisect(lambda th: learn.rms_error(T64.forces(th, eps)[0], a_ref, tg), 0.1, 1.1, target)
             i64, ms64 = run(T64, theta=th64)
             out["fixed_fp64"] = dict(theta=th64, rms=e64, interactions=i64, walk_ms=ms64)

@@ -126,8 +126,10 @@ BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double ep
  * those of the same cluster built alone.  If lists != NULL it also writes the first maxlen
  * words of each list to lists [n][maxlen] (entries past the list are left as
  * they were).  If group_steps != NULL it receives, per group of 64 targets of
- * the walk (ceil(n/64) int32), the number of nodes the group's wavefront
- * visited: sum(counts) / (64 * sum(group_steps)) is the share of useful lanes. */
+ * the walk (ceil(n/64) int32; group g is the g-th run of 64 targets of the
+ * walk's target order, so the Morton groups only under target_order 0), the
+ * number of nodes the group's wavefront visited: sum(counts) / (64 *
+ * sum(group_steps)) is the share of useful lanes. */
 BH_API int bh_walk_stats(const bh_tree *t, double theta, const float *theta_group, double eps, void *acc,
                   void *pot, int32_t *counts, uint64_t *hash, int64_t *lists, int64_t maxlen,
                   int32_t *group_steps, void *stream);

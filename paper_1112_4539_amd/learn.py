@@ -81,6 +81,8 @@ def label_snapshot(pos, mass, eps, grid=THETA_GRID, target=TARGET):
     per-group error and cost tables R, C [len(grid), G]."""
     gp, gm = _dev(pos, torch.float32), _dev(mass, torch.float32)
     T = bh.Tree(gp, gm)
+    # costs per Morton group, the groups a per-group theta belongs to
+    T.set_walk_config(target_order=0)
     X = T.features()
     # the reference sees exactly the FP32 values the walk sees
     a_ref, _ = bh.direct(gp.double(), gm.double(), eps)
@@ -106,6 +108,7 @@ def label_sampled(pos, mass, eps, n_groups, seed, grid=THETA_GRID, target=TARGET
     only the sampled groups' 64 S targets."""
     gp, gm = _dev(pos, torch.float32), _dev(mass, torch.float32)
     T = bh.Tree(gp, gm)
+    T.set_walk_config(target_order=0)  # costs per Morton group, as in label_snapshot
     X = T.features()
     n, G = T.n, T.n_groups
     n_groups = min(n_groups, G - 1)
