@@ -348,7 +348,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=262144)
     ap.add_argument("--waves-per-block", type=int, default=1)
-    ap.add_argument("--xcd-chunk", type=int, default=0)
+    ap.add_argument("--xcd-chunk", type=int, default=-1)
     ap.add_argument("--target-order", type=int, default=2)
     ap.add_argument("--lds-share", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0)

@@ -141,8 +141,12 @@ BH_API int bh_walk_stats(const bh_tree *t, double theta, const float *theta_grou
  * caller index).  Either pointer may be NULL.  Synchronises the stream. */
 BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *stream);
 
-/* Launch shape of the walk: waves_per_block in {1, 2, 4}; xcd_chunk >= 0
- * (runs of workgroups kept on one XCD; 0 = plain order).  target_order 0 =
+/* Launch shape of the walk: waves_per_block in {1, 2, 4}; xcd_chunk >= -1
+ * (runs of workgroups kept on one XCD; 0 = plain order; -1, the default, =
+ * 1024 for FP32 trees, about as many one-wave workgroups as an XCD holds at
+ * once, so that an XCD's resident waves walk neighbouring groups and share its
+ * L2, and 0 for FP64 trees, whose walk measured slower with runs; a run is
+ * capped at a 64th of the grid so that every XCD takes at least 8 runs).  target_order 0 =
  * Morton order (groups of Morton-consecutive targets), 1 = caller order (the
  * paper's unsorted experiment, Sec. 5), 2 = Hilbert order (the default):
  * targets sorted by cluster and the Hilbert index of their cell ten levels

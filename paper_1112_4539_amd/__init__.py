@@ -196,7 +196,7 @@ class Tree:
                                     ctypes.byref(c)))
         return dict(n_nodes=a.value, n_leaves=b.value, n_internal=c.value)
 
-    def set_walk_config(self, waves_per_block=1, xcd_chunk=0, target_order=2, lds_share=0, persistent=0,
+    def set_walk_config(self, waves_per_block=1, xcd_chunk=-1, target_order=2, lds_share=0, persistent=0,
                         targets_per_lane=1):
         _check(load().bh_set_walk_config(self._h, int(waves_per_block), int(xcd_chunk), int(target_order),
                                          int(lds_share), int(persistent), int(targets_per_lane)))

@@ -26,7 +26,7 @@ struct bh_tree {
   int32_t* rank = nullptr;  // caller index -> Morton position
   int32_t* queue = nullptr; // group counter of the persistent walk
   int waves_per_block = 1;
-  int xcd_chunk = 0;
+  int xcd_chunk = -1;  // -1: 1024 for FP32 trees (about the one-wave workgroups an XCD holds), 0 for FP64
   int target_order = 2;
   mutable bool horder_ready = false;  // w.horder holds the Hilbert order of the current build
   int lds_share64 = 0;
@@ -213,7 +213,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.lists = lists;
   a.maxlen = maxlen;
   a.group_steps = group_steps;
-  a.xcd_chunk = t->xcd_chunk;
+  a.xcd_chunk = t->xcd_chunk >= 0 ? t->xcd_chunk : (t->prec == BH_FP64 ? 0 : 1024);
   a.lds_share64 = t->lds_share64;
   a.waves_per_block = t->waves_per_block;
   a.persistent = t->persistent;
@@ -361,7 +361,7 @@ int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int targe
   if (!t) return fail(BH_EINVAL, "null tree");
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return fail(BH_EINVAL, "waves_per_block must be 1, 2 or 4");
-  if (xcd_chunk < 0) return fail(BH_EINVAL, "xcd_chunk must be >= 0");
+  if (xcd_chunk < -1) return fail(BH_EINVAL, "xcd_chunk must be >= -1");
   if (target_order < 0 || target_order > 2) return fail(BH_EINVAL, "target_order must be 0, 1 or 2");
   if (lds_share < 0 || lds_share > 64) return fail(BH_EINVAL, "lds_share must be in [0, 64]");
   if (persistent != 0 && persistent != 1) return fail(BH_EINVAL, "persistent must be 0 or 1");
@@ -533,11 +533,11 @@ int bh_autotune(bh_tree* t, double theta, double eps, void* acc, void* pot, int 
   static const int kPersistent[] = {0, 1};
   static const int kWpb[] = {1, 2, 4};
   static const int kShare[] = {0, 8, 16, 32};
-  static const int kChunk[] = {0, 2, 8};
+  static const int kChunk[] = {0, 8, 256, 1024};
   for (int stage = 0; stage < 5 && rc == BH_OK; ++stage) {
     const int* vals = stage == 0 ? kTargets : stage == 1 ? kPersistent : stage == 2 ? kWpb : stage == 3 ? kShare
                                                                                                         : kChunk;
-    const int nv = stage == 0 ? 2 : stage == 1 ? 2 : stage == 2 ? 3 : stage == 3 ? 4 : 3;
+    const int nv = stage == 0 ? 2 : stage == 1 ? 2 : stage == 2 ? 3 : stage == 3 ? 4 : 4;
     if (stage == 4 && cur.persistent) break;  // the block remap does not apply to the persistent walk
     bh_walk_config stage_best = cur;
     for (int v = 0; v < nv; ++v) {

@@ -37,9 +37,12 @@ namespace bh {
 
 __device__ __forceinline__ int remap_block(int b, int nb, int chunk) {
   // Workgroups are dispatched to the 8 XCDs round-robin.  Give each XCD runs of
-  // `chunk` consecutive workgroups (Morton-adjacent groups share tree nodes in
+  // `chunk` consecutive workgroups (neighbouring groups share tree nodes in
   // that XCD's L2), interleaving the runs across XCDs to keep the load even.
+  // A run is at most a 64th of the grid, so that every XCD takes at least 8
+  // runs and a few heavy runs do not leave the other XCDs idle at the end.
   if (chunk <= 0) return b;
+  chunk = min(chunk, max(1, nb >> 6));
   const int full = (nb / (8 * chunk)) * 8 * chunk;
   if (b >= full) return b;
   const int k = b >> 3, x = b & 7;
