@@ -228,6 +228,25 @@ def test_launch_shapes_and_target_order_bitexact(bh):
                                                                                        pers, tpl)
 
 
+def test_walk_config_values(bh):
+    """The launch-shape knobs reject values outside their ranges; -1 (automatic
+    XCD runs) and every target order give the same bits."""
+    say("[config] knob ranges, plummer 20k fp32 and fp64")
+    pos, mass = inputs.plummer(20_000, 21)
+    for prec in ("fp32", "fp64"):
+        T = bh.Tree(*_gpu(pos, mass, prec))
+        ref = T.forces(0.5, 0.01)
+        for bad in (dict(xcd_chunk=-2), dict(target_order=3), dict(target_order=-1), dict(waves_per_block=3),
+                    dict(lds_share=65), dict(persistent=2), dict(targets_per_lane=3)):
+            with pytest.raises(ValueError):
+                T.set_walk_config(**bad)
+        for chunk in (-1, 0, 1, 1024, 1 << 20):
+            for order in (0, 1, 2):
+                T.set_walk_config(xcd_chunk=chunk, target_order=order)
+                a, p = T.forces(0.5, 0.01)
+                assert torch.equal(a, ref[0]) and torch.equal(p, ref[1]), (prec, chunk, order)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_edge_cases(bh, prec):
     say(f"[edge] {prec}")
