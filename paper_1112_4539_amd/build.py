@@ -19,8 +19,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall",
 ]
-# The walk prefetches the two possible successor nodes at the top of each
-# step; machine sinking would move those loads down next to their use.
+# The walk issues the next node record's load as soon as the opening test has
+# fixed the cursor, ahead of the terms; machine sinking would move that load
+# down into the next step, next to its use.
 EXTRA = {"bh_walk.hip": ["-mllvm", "-disable-machine-sink"]}
 BUILD_DIR = os.path.join(HERE, "_build")
 
