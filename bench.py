@@ -153,6 +153,7 @@ def sweep_bench(args, bh, inputs):
     the walk time with targets in Hilbert order (the default), in Morton order and in the input
     (random) order; the FP64 walk
     beside it as the accuracy reference of the FP32 arithmetic."""
+    from paper_1112_4539_amd import metrics
     pos, mass, spec = inputs.make("plummer1m")
     eps = spec["eps"]
     n = len(pos)
@@ -180,17 +181,16 @@ def sweep_bench(args, bh, inputs):
         st = T32.walk_stats(theta, eps)
         inter = int(st["counts"].to(torch.int64).sum().item())
         steps = int(st["group_steps"].to(torch.int64).sum().item())
-        d = (st["acc"][tg].double() - a_ref).norm(dim=1) / a_ref.norm(dim=1)
         a64, _ = T64.forces(theta, eps)
-        d64 = (a64[tg] - a_ref).norm(dim=1) / a_ref.norm(dim=1)
-        d3264 = (st["acc"][tg].double() - a64[tg]).norm(dim=1) / a64[tg].norm(dim=1)
+        d3264 = metrics.rel_errors(st["acc"][tg], a64[tg])
         ms_m = walk_ms(T32, theta, 0, max(3, args.steps))
         ms_h = walk_ms(T32, theta, 2, max(3, args.steps))
         ms_r = walk_ms(T32, theta, 1, 2)
         ms_64 = walk_ms(T64, theta, 2, 3)
         row = dict(theta=theta, interactions=inter, mean_list=inter / n, lane_efficiency=inter / (64.0 * steps),
-                   rms_rel_err=float(torch.sqrt(torch.mean(d * d))), mean_rel_err=float(d.mean()),
-                   rms_rel_err_fp64_walk=float(torch.sqrt(torch.mean(d64 * d64))),
+                   rms_rel_err=metrics.rms_rel_err(st["acc"][tg], a_ref),
+                   mean_rel_err=metrics.mean_rel_err(st["acc"][tg], a_ref),
+                   rms_rel_err_fp64_walk=metrics.rms_rel_err(a64[tg], a_ref),
                    max_rel_diff_fp32_vs_fp64_walk=float(d3264.max()),
                    walk_ms_morton=ms_m, walk_ms_hilbert=ms_h, walk_ms_random_order=ms_r,
                    random_over_morton=ms_r / ms_m, walk_ms_fp64=ms_64, interactions_per_s=inter / (ms_h * 1e-3))
@@ -363,6 +363,7 @@ def main():
 
     import paper_1112_4539_amd as bh
     from paper_1112_4539_amd import inputs
+    from paper_1112_4539_amd import metrics
 
     if args.workload == "clusters512":
         return forest_bench(args, bh, inputs)
@@ -456,8 +457,7 @@ def main():
         a_ref, _ = bh.direct(gpos.double(), gmass.double(), eps, tg)
         T = bh.Tree(gpos, gmass, workspace=ws)
         a, _ = T.forces(args.theta, eps, acc=acc, pot=pot)
-        d = (a[tg].double() - a_ref).norm(dim=1) / a_ref.norm(dim=1)
-        rms = float(torch.sqrt(torch.mean(d * d)).item())
+        rms = metrics.rms_rel_err(a[tg], a_ref)
         log(f"[bench] RMS rel force err vs FP64 direct on {args.samples} targets: {rms:.3e}")
 
     value = inter / (ms_step * 1e-3)

@@ -73,7 +73,7 @@ BH_API int bh_version(void);
 
 /* Bytes of workspace a tree of n particles in precision prec needs (an upper
  * bound: the compressed oct-tree has at most 2n-1 nodes).  Returns -1 for an
- * invalid n (n < 0 or n > 2^30) or prec. */
+ * invalid n (n < 0 or n > 2^30 - 1: node and record indices are 32-bit) or prec. */
 BH_API int64_t bh_workspace_bytes(int64_t n, int prec);
 
 /* Build the tree of n particles (Sec. 4.1 construction; Sec. 5 Morton order;
@@ -92,7 +92,9 @@ BH_API int bh_build_tree(const void *pos, const void *mass, int64_t n, int prec,
                   int64_t ws_bytes, void *stream, bh_tree **out);
 
 /* Synchronise `stream` and report whether the inputs of the build were finite
- * (BH_EINVAL if not) and whether the GPU work failed (BH_EHIP). */
+ * (BH_EINVAL if not), whether the last per-group-theta walk met an invalid
+ * theta (BH_EINVAL; see bh_forces_theta) and whether the GPU work failed
+ * (BH_EHIP). */
 BH_API int bh_tree_check(const bh_tree *t, void *stream);
 
 /* Synchronise `stream` and read the node counts of the tree (any pointer may be NULL). */
@@ -111,8 +113,10 @@ BH_API int bh_tree_stats(const bh_tree *t, void *stream, int64_t *n_nodes, int64
 BH_API int bh_forces(const bh_tree *t, double theta, double eps, void *acc, void *pot, void *stream);
 
 /* Same walk with one opening parameter per Morton group of 64 particles:
- * theta_group [ceil(n/64)] device floats, each in (0, 2/sqrt(3)) (not checked
- * on the device); group g holds the particles at Morton positions [64g, 64g+64). */
+ * theta_group [ceil(n/64)] device floats, each in (0, 2/sqrt(3)); group g holds
+ * the particles at Morton positions [64g, 64g+64).  A value that is not finite
+ * or lies outside that range is replaced by 0.5 on the device, and the next
+ * bh_tree_check() reports it (BH_EINVAL) until the next per-group walk. */
 BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double eps, void *acc, void *pot,
                     void *stream);
 

@@ -197,14 +197,21 @@ def features(tree, pos, mass):
 
 
 def group_rms(acc, acc_ref, perm):
-    """Per Morton group: RMS over its particles of |a - a_ref| / |a_ref| (caller-order inputs)."""
+    """Per Morton group: RMS over its particles of |a - a_ref| / |a_ref| (caller-order inputs).
+
+    The relative error of Eq. (4) is undefined where a_ref = 0: such particles are left out of
+    their group's mean, and a group with none left has RMS 0."""
     acc = np.asarray(acc, np.float64)[perm]
     ref = np.asarray(acc_ref, np.float64)[perm]
-    d = np.linalg.norm(acc - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    den = np.linalg.norm(ref, axis=1)
+    ok = den > 0
+    d = np.zeros(len(den))
+    d[ok] = np.linalg.norm(acc - ref, axis=1)[ok] / den[ok]
     n = len(d)
     G = (n + 63) // 64
     out = np.zeros(G)
     for g in range(G):
-        s = d[64 * g:min(n, 64 * g + 64)]
-        out[g] = np.sqrt(np.mean(s * s))
+        sl = slice(64 * g, min(n, 64 * g + 64))
+        s = d[sl][ok[sl]]
+        out[g] = np.sqrt(np.mean(s * s)) if len(s) else 0.0
     return out

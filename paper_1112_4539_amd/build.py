@@ -7,6 +7,7 @@ expression order exactly); packed FP32 instructions disabled.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -38,14 +39,17 @@ def _run(cmd, verbose):
         raise RuntimeError(f"hipcc failed with status {r.returncode}: {' '.join(cmd)}")
 
 
-def build(verbose=False):
-    """Compile the library in-tree (one object per source, then link); returns the path of libbh.so."""
+def build(verbose=False, jobs=None):
+    """Compile the library in-tree (one object per source, compiled side by side, then link);
+    returns the path of libbh.so."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
-        _run([HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", "-o", obj, os.path.join(CSRC, src)], verbose)
-        objs.append(obj)
+    objs = [os.path.join(BUILD_DIR, src.replace(".hip", ".o")) for src in SOURCES]
+    cmds = [[HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", "-o", obj, os.path.join(CSRC, src)]
+            for src, obj in zip(SOURCES, objs)]
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950:xnack-", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)

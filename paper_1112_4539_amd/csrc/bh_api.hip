@@ -58,10 +58,11 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(BH_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-constexpr int64_t kMaxN = int64_t(1) << 30;
+// (node and record indices are int32: 2n + 1 walk records must fit)
+constexpr int64_t kMaxN = (int64_t(1) << 30) - 1;
 constexpr int64_t kMaxClusters = int64_t(1) << 24;
 constexpr size_t kAlign = 256;
-const double kThetaMax = 2.0 / std::sqrt(3.0);
+using bh::kThetaMax;
 const double kThetaCap = 1.15;  // largest learned theta handed to the walk (below 2/sqrt(3))
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -179,7 +180,12 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   if (!theta_group) {
     hipError_t e = bh::launch_mac_size(t->w.nodes, t->w.counts, (int)(2 * t->n), 1.0 / theta, t->w.wnodes, st);
     if (e != hipSuccess) return hip_fail(e, "launching the opening-size pass");
-  } else if (t->prec == BH_FP32) {
+  } else {
+    // the flag reports this walk's per-group values only
+    hipError_t e = bh::fill_i32(&t->w.counts->bad_theta, 1, 0, st);
+    if (e != hipSuccess) return hip_fail(e, "clearing the theta flag");
+  }
+  if (theta_group && t->prec == BH_FP32) {
     hipError_t e = bh::launch_theta_copy(t->w.nodes, t->w.counts, (int)(2 * t->n),
                                          reinterpret_cast<bh::ThetaNode*>(t->w.wnodes), st);
     if (e != hipSuccess) return hip_fail(e, "launching the per-group walk copy");
@@ -193,6 +199,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   bh::WalkArgs a{};
   a.nodes = t->w.nodes;
   a.cnt = t->w.counts;
+  a.bad_theta = &t->w.counts->bad_theta;
   a.wnodes = t->w.wnodes;
   a.tnodes = reinterpret_cast<const bh::ThetaNode*>(t->w.wnodes);
   a.ps = t->w.ps;
@@ -260,7 +267,7 @@ int bh_build_forest(const void* pos, const void* mass, const int64_t* offsets, i
                     int prec, void* workspace, int64_t ws_bytes, void* stream, bh_tree** out) {
   if (!out) return fail(BH_EINVAL, "out must not be null");
   *out = nullptr;
-  if (n < 0 || n > kMaxN) return fail(BH_EINVAL, "n must be in [0, 2^30]; got %lld", (long long)n);
+  if (n < 0 || n > kMaxN) return fail(BH_EINVAL, "n must be in [0, 2^30 - 1]; got %lld", (long long)n);
   if (n_clusters < 1 || n_clusters > kMaxClusters)
     return fail(BH_EINVAL, "n_clusters must be in [1, 2^24]; got %lld", (long long)n_clusters);
   if (prec != BH_FP32 && prec != BH_FP64) return fail(BH_EINVAL, "prec must be BH_FP32 or BH_FP64");
@@ -302,6 +309,9 @@ int bh_tree_check(const bh_tree* t, void* stream) {
   int rc = sync_counts(t, static_cast<hipStream_t>(stream), &c);
   if (rc) return rc;
   if (c.bad_input) return fail(BH_EINVAL, "non-finite particle coordinate or mass");
+  if (c.bad_theta)
+    return fail(BH_EINVAL, "a per-group theta was not finite or outside (0, 2/sqrt(3)); %g was used in its place",
+                (double)bh::kThetaFallback);
   return BH_OK;
 }
 
@@ -405,7 +415,7 @@ void bh_tree_release(bh_tree* t) {
 
 int bh_direct(const void* pos, const void* mass, int64_t n, int prec, const int64_t* targets, int64_t nt,
               double eps, void* acc, void* pot, void* stream) {
-  if (n < 0 || n > kMaxN || nt < 0 || nt > kMaxN) return fail(BH_EINVAL, "n and nt must be in [0, 2^30]");
+  if (n < 0 || n > kMaxN || nt < 0 || nt > kMaxN) return fail(BH_EINVAL, "n and nt must be in [0, 2^30 - 1]");
   if (prec != BH_FP32 && prec != BH_FP64) return fail(BH_EINVAL, "prec must be BH_FP32 or BH_FP64");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BH_EINVAL, "eps must be finite and >= 0; got %g", eps);
   if (nt == 0) return BH_OK;
@@ -591,7 +601,7 @@ int bh_group_error(const bh_tree* t, const void* acc, const double* acc_ref, dou
 }
 
 int bh_mlp_sizes(int64_t batch, int64_t* n_param, int64_t* n_grad, int64_t* n_wbf16, int64_t* n_partial) {
-  if (batch < 0 || batch > kMaxN) return fail(BH_EINVAL, "batch must be in [0, 2^30]");
+  if (batch < 0 || batch > kMaxN) return fail(BH_EINVAL, "batch must be in [0, 2^30 - 1]");
   if (n_param) *n_param = bh::kMlpParams;
   if (n_grad) *n_grad = bh::kMlpGradLen;
   if (n_wbf16) *n_wbf16 = bh::kMlpWb;
@@ -609,7 +619,7 @@ int bh_mlp_prepare(const float* params, uint16_t* wbf16, void* stream) {
 
 int bh_mlp_infer(const float* params, const uint16_t* wbf16, const float* norm, const float* X, int64_t rows,
                  float alpha, float theta_fallback, float* theta, void* stream) {
-  if (rows < 0 || rows > kMaxN) return fail(BH_EINVAL, "rows must be in [0, 2^30]");
+  if (rows < 0 || rows > kMaxN) return fail(BH_EINVAL, "rows must be in [0, 2^30 - 1]");
   if (rows == 0) return BH_OK;
   if (!params || !wbf16 || !norm || !X || !theta || !aligned(wbf16, 16) || !aligned(X, 4) || !aligned(theta, 4))
     return fail(BH_EINVAL, "null or misaligned device array");
@@ -624,7 +634,7 @@ int bh_mlp_infer(const float* params, const uint16_t* wbf16, const float* norm, 
 
 int bh_mlp_grad(const float* params, const uint16_t* wbf16, const float* norm, const float* X, const float* target,
                 const int32_t* rows_idx, int64_t batch, float* partial, float* grad, void* stream) {
-  if (batch < 1 || batch > kMaxN) return fail(BH_EINVAL, "batch must be in [1, 2^30]");
+  if (batch < 1 || batch > kMaxN) return fail(BH_EINVAL, "batch must be in [1, 2^30 - 1]");
   if (!params || !wbf16 || !norm || !X || !target || !rows_idx || !partial || !grad || !aligned(wbf16, 16) ||
       !aligned(rows_idx, 4) || !aligned(partial, 4) || !aligned(grad, 4))
     return fail(BH_EINVAL, "null or misaligned device array");

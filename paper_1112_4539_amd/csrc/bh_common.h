@@ -87,8 +87,15 @@ struct Counts {
   int32_t n_internal;   // I: internal nodes
   int32_t n_nodes;      // U + I
   int32_t bad_input;    // nonzero if a coordinate or mass was not finite
-  int32_t pad[4];
+  int32_t bad_theta;    // nonzero if the last per-group-theta walk met an invalid theta
+  int32_t pad[3];
 };
+
+// Opening parameters: a walk accepts theta in (0, 2/sqrt(3)) (beyond that a cell
+// holding the target could pass Eq. (2)); a per-group theta outside that range
+// or not finite is replaced by kThetaFallback and reported.
+constexpr double kThetaMax = 1.1547005383792515;  // 2/sqrt(3)
+constexpr float kThetaFallback = 0.5f;
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 

@@ -73,6 +73,7 @@ hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st);
 struct WalkArgs {
   const Node* nodes;
   const Counts* cnt;           // the build's counters (leaf count)
+  int32_t* bad_theta;          // per-group theta walks: set to 1 if a theta was replaced
   const void* ps;              // float4 / double4 particles in Morton order
   const int32_t* perm;         // Morton position -> caller index
   const int32_t* order;        // optional target order (Morton positions), may be null

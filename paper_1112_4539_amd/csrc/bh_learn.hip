@@ -177,14 +177,21 @@ __global__ __launch_bounds__(256) void k_group_error(const R* __restrict__ acc, 
   const int a = 64 * g;
   if (a >= n) return;
   const int b = min(n, a + 64);
+  // (a particle whose reference force is exactly zero has no relative error:
+  // it is left out, and a group of only such particles has RMS 0)
   double s = 0.0;
+  int m = 0;
   for (int q = a; q < b; ++q) {
     const int64_t o = perm[q];
     const double rx = ref[3 * o], ry = ref[3 * o + 1], rz = ref[3 * o + 2];
     const double dx = (double)acc[3 * o] - rx, dy = (double)acc[3 * o + 1] - ry, dz = (double)acc[3 * o + 2] - rz;
-    s += (dx * dx + dy * dy + dz * dz) / (rx * rx + ry * ry + rz * rz);
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 > 0.0) {
+      s += (dx * dx + dy * dy + dz * dz) / r2;
+      ++m;
+    }
   }
-  const double r = sqrt(s / (double)(b - a));
+  const double r = m > 0 ? sqrt(s / (double)m) : 0.0;
   if (rms) rms[g] = r;
   if (label && r <= target) label[g] = fmaxf(label[g], (float)theta);
 }

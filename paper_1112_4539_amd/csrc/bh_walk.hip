@@ -604,7 +604,18 @@ __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (
     T.xi = (double)me.x;
     T.yi = (double)me.y;
     T.zi = (double)me.z;
-    T.inv_theta = kGroupTheta ? 1.0 / (double)a.theta_group[valid ? (T.i >> 6) : 0] : a.inv_theta;
+    if constexpr (kGroupTheta) {
+      // theta of the target's Morton group; one that is not finite or outside
+      // (0, 2/sqrt(3)) is replaced by the fallback and reported
+      float th = valid ? a.theta_group[T.i >> 6] : kThetaFallback;
+      if (!(th > 0.f && (double)th < kThetaMax)) {
+        th = kThetaFallback;
+        atomicOr(a.bad_theta, 1);
+      }
+      T.inv_theta = 1.0 / (double)th;
+    } else {
+      T.inv_theta = a.inv_theta;
+    }
     T.acc.init();
     T.n_pp = T.n_pc = 0;
     T.h = kFnvOffset;

@@ -32,7 +32,7 @@ import numpy as np
 import torch
 
 import paper_1112_4539_amd as bh
-from paper_1112_4539_amd import inputs
+from paper_1112_4539_amd import inputs, metrics
 
 THETA_GRID = tuple(round(0.20 + 0.05 * k, 2) for k in range(17))
 TARGET = 1e-3
@@ -53,14 +53,28 @@ def _dev(a, dtype):
 
 def allocate(R, C, n_g, target):
     """Cost-optimal grid index per group: argmin_k C[k,g] + lam n_g R[k,g]^2 with lam such that
-    sqrt(sum_g n_g R[k_g,g]^2 / N) is at most (and close to) the target."""
+    sqrt(sum_g n_g R[k_g,g]^2 / N) is at most (and close to) the target.
+
+    Entries whose error or cost is not finite are never chosen; a group with no finite entry at
+    all takes grid index 0 (the smallest theta) and is left out of the error sum, so that one
+    bad group cannot move the allocation of the others."""
+    R = np.asarray(R, np.float64)
+    C = np.asarray(C, np.float64)
+    n_g = np.asarray(n_g, np.float64)
     E = n_g[None, :] * R * R
-    N = float(n_g.sum())
+    ok = np.isfinite(E) & np.isfinite(C)
+    E = np.where(ok, E, np.inf)
+    Cm = np.where(ok, C, np.inf)
+    dead = ~ok.any(axis=0)
+    live = ~dead
+    N = float(n_g[live].sum()) if live.any() else 1.0
     cols = np.arange(R.shape[1])
 
     def pick(lam):
-        k = np.argmin(C + lam * E, axis=0)
-        return k, np.sqrt(E[k, cols].sum() / N)
+        with np.errstate(invalid="ignore"):
+            k = np.argmin(Cm + lam * E, axis=0)
+        k[dead] = 0
+        return k, np.sqrt(E[k[live], cols[live]].sum() / N)
 
     lo, hi = 0.0, 40.0      # log10 of lambda
     k, err = pick(10.0 ** hi)
@@ -211,8 +225,7 @@ def scaled_theta(raw, alpha, beta, cap=1.15):
 
 def rms_error(acc, a_ref, targets):
     """RMS of |a - a_ref| / |a_ref| over the sampled targets (a_ref float64 [len(targets), 3])."""
-    d = (acc[targets].double() - a_ref).norm(dim=1) / a_ref.norm(dim=1)
-    return float(torch.sqrt(torch.mean(d * d)).item())
+    return metrics.rms_rel_err(acc[targets], a_ref)
 
 
 def bisect(f, lo, hi, target, rel=0.02, iters=40):

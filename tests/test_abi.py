@@ -43,6 +43,8 @@ def test_host_side_argument_checks():
     assert lib.bh_version() == 2
     assert lib.bh_workspace_bytes(-1, 0) == -1
     assert lib.bh_workspace_bytes(1 << 31, 0) == -1
+    assert lib.bh_workspace_bytes(1 << 30, 0) == -1          # indices are 32-bit: n <= 2^30 - 1
+    assert lib.bh_workspace_bytes((1 << 30) - 1, 0) > 0
     assert lib.bh_workspace_bytes(10, 7) == -1
     w1 = lib.bh_workspace_bytes(1000, 0)
     w2 = lib.bh_workspace_bytes(1000, 1)

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_1112_4539_amd import inputs
-from tests.util import force_err, pot_err
+from tests.util import check_forces, pot_err
 
 pytestmark = pytest.mark.gpu
 
@@ -128,7 +128,7 @@ def test_forest_against_oracle(bh, prec):
         np.testing.assert_array_equal(st["lists"][b:e].cpu().numpy(), w["lists"])
         acc = st["acc"][b:e].cpu().numpy().astype(np.float64)
         pot = st["pot"][b:e].cpu().numpy().astype(np.float64)
-        assert force_err(acc, w["acc"], w["amag"]).max() <= tol, k
+        check_forces(acc, w["acc"], w["amag"], tol, f"cluster {k}", log=say)
         assert pot_err(pot, w["pot"]).max() <= tol, k
 
 
@@ -193,7 +193,7 @@ def test_forest_full_size(bh):
         np.testing.assert_array_equal(cnt[:, 1], w["n_pc"])
         np.testing.assert_array_equal(st["hash"][b:e].cpu().numpy().view(np.uint64)[tg], w["hash"])
         acc = st["acc"][b:e].cpu().numpy()[tg].astype(np.float64)
-        assert force_err(acc, w["acc"], w["amag"]).max() <= F32_TOL
+        check_forces(acc, w["acc"], w["amag"], F32_TOL, "forest", log=say)
     # persistent walk of the whole forest: same bits
     a0, p0 = st["acc"], st["pot"]
     for tpl in (1, 2):

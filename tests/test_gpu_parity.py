@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_1112_4539_amd import inputs
-from tests.util import force_err, pot_err, tree_cases, widen
+from tests.util import check_forces, force_err, pot_err, tree_cases, widen
 
 pytestmark = pytest.mark.gpu
 
@@ -123,9 +123,8 @@ def test_lists_and_forces_plummer4k_fp64(bh, tpl):
     say(f"[walk] plummer4k fp64 theta=0.5 full list dump, {tpl} targets per lane")
     pos, mass = inputs.plummer(4096, 0)
     acc, pot, w = _walk_compare(bh, pos, mass, "fp64", 0.5, 0.01, maxlen=4096, tpl=tpl)
-    e = force_err(acc, w["acc"], w["amag"])
-    say(f"  max err {e.max():.3e}  bit-exact share {np.mean(np.all(acc == w['acc'], axis=1)):.4f}")
-    assert e.max() <= F64_TOL
+    check_forces(acc, w["acc"], w["amag"], F64_TOL, "fp64", log=say)
+    say(f"  bit-exact share {np.mean(np.all(acc == w['acc'], axis=1)):.4f}")
     assert pot_err(pot, w["pot"]).max() <= F64_TOL
 
 
@@ -135,9 +134,7 @@ def test_lists_and_forces_plummer4k_fp32(bh, theta, tpl):
     say(f"[walk] plummer4k fp32 theta={theta} full list dump, {tpl} targets per lane")
     pos, mass = inputs.plummer(4096, 0)
     acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, 0.01, maxlen=4096, tpl=tpl)
-    e = force_err(acc, w["acc"], w["amag"])
-    say(f"  max err {e.max():.3e} p99 {np.quantile(e, 0.99):.3e}")
-    assert e.max() <= F32_TOL
+    check_forces(acc, w["acc"], w["amag"], F32_TOL, "fp32", log=say)
     assert pot_err(pot, w["pot"]).max() <= F32_TOL
 
 
@@ -149,7 +146,7 @@ def test_lists_theta_above_one(bh, prec, theta):
     pos, mass = inputs.plummer(4096, 0)
     acc, pot, w = _walk_compare(bh, pos, mass, prec, theta, 0.01, maxlen=4096)
     tol = F32_TOL if prec == "fp32" else F64_TOL
-    assert force_err(acc, w["acc"], w["amag"]).max() <= tol
+    check_forces(acc, w["acc"], w["amag"], tol, prec, log=say)
     assert pot_err(pot, w["pot"]).max() <= tol
 
 
@@ -162,10 +159,8 @@ def test_theta_per_group(bh, prec, tpl):
     g = (len(pos) + 63) // 64
     tg = np.random.default_rng(3).uniform(0.2, 1.15, g).astype(np.float32)
     acc, pot, w = _walk_compare(bh, pos, mass, prec, 0.5, 1e-4, theta_group=tg, tpl=tpl)
-    e = force_err(acc, w["acc"], w["amag"])
-    say(f"  max err {e.max():.3e}")
     tol = F32_TOL if prec == "fp32" else F64_TOL
-    assert e.max() <= tol
+    check_forces(acc, w["acc"], w["amag"], tol, prec, log=say)
     assert pot_err(pot, w["pot"]).max() <= tol
 
 
@@ -177,9 +172,8 @@ def test_direct_fp64_matches_definition(bh):
     acc, pot = bh.direct(gp, gm, 0.01, tg)
     a_ref, p_ref, amag = oracle.direct(pos, mass, 0.01)
     acc = acc.cpu().numpy()
-    e = force_err(acc, a_ref, amag)
-    say(f"  max err {e.max():.3e} bit-exact share {np.mean(acc == a_ref):.4f}")
-    assert e.max() <= F64_TOL
+    check_forces(acc, a_ref, amag, F64_TOL, "direct fp64", log=say)
+    say(f"  bit-exact share {np.mean(acc == a_ref):.4f}")
     assert pot_err(pot.cpu().numpy(), p_ref).max() <= F64_TOL
 
 
@@ -294,9 +288,8 @@ def test_full_size_sampled(bh, name, theta, tpl):
     pos, mass, spec = inputs.make(name)
     tg = inputs.sample_targets(len(pos), 2048, spec["seed"] + 100)
     acc, pot, w = _walk_compare(bh, pos, mass, "fp32", theta, spec["eps"], targets=tg, tpl=tpl)
-    e = force_err(acc, w["acc"], w["amag"])
-    say(f"  max err {e.max():.3e}  p99 {np.quantile(e, 0.99):.3e}  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
-    assert e.max() <= F32_TOL
+    check_forces(acc, w["acc"], w["amag"], F32_TOL, name, log=say)
+    say(f"  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
     assert pot_err(pot, w["pot"]).max() <= F32_TOL
 
 
@@ -310,7 +303,61 @@ def test_walk_copy_above_4gib(bh):
     mass = np.full(n, 1.0 / n)
     tg = inputs.sample_targets(n, 256, 17)
     acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.6, 1e-3, targets=tg)
-    e = force_err(acc, w["acc"], w["amag"])
-    say(f"  max err {e.max():.3e}  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
-    assert e.max() <= F32_TOL
+    check_forces(acc, w["acc"], w["amag"], F32_TOL, "cube 2^25+4097", log=say)
+    say(f"  mean L {np.mean(w['n_pp'] + w['n_pc']):.0f}")
     assert pot_err(pot, w["pot"]).max() <= F32_TOL
+
+
+def test_theta_per_group_invalid_values(bh):
+    """Per-group theta values that are not finite or outside (0, 2/sqrt(3)) are replaced by 0.5 on the
+    device and reported by the check; the other groups are untouched, and a walk with valid values
+    clears the report."""
+    say("[walk] per-group theta with invalid entries, clumpy 20k fp32")
+    pos, mass = inputs.clumpy(20_000, 33)
+    g = (len(pos) + 63) // 64
+    tg = np.random.default_rng(4).uniform(0.3, 1.0, g).astype(np.float32)
+    bad = {3: np.nan, 7: 0.0, 11: -0.5, 13: 1.2, 17: np.inf, 19: -np.inf}
+    for k, v in bad.items():
+        tg[k] = v
+    gp, gm = _gpu(pos, mass, "fp32")
+    T = bh.Tree(gp, gm)
+    out = T.walk_stats(0.5, 1e-4, theta_group=torch.tensor(tg, device="cuda"))
+    with pytest.raises(ValueError, match="theta"):
+        T.check()
+    fixed = tg.copy()
+    for k in bad:
+        fixed[k] = 0.5
+    p64, m64 = _seen(pos, mass, "fp32")
+    O = oracle.Tree(p64, m64)
+    rank = np.empty(len(pos), np.int64)
+    rank[O.perm] = np.arange(len(pos))
+    w = O.walk(0.5, 1e-4, theta_per_target=fixed.astype(np.float64)[rank // 64])
+    np.testing.assert_array_equal(out["hash"].cpu().numpy().view(np.uint64), w["hash"])
+    check_forces(out["acc"].cpu().numpy(), w["acc"], w["amag"], F32_TOL, "fallback", log=say)
+    T.forces(0.5, 1e-4, theta_group=torch.tensor(fixed, device="cuda"))
+    T.check()
+
+
+def test_theta_per_group_full_size(bh):
+    """The per-group theta walk at the size the learned-theta runs use it (clumpy 4M, FP32), theta_g drawn
+    in [0.2, 1.15]: counts, ordered-list hashes and forces of 2048 sampled targets against the oracle's
+    per-target-theta walk."""
+    say("[full] clumpy4m per-group theta in [0.2, 1.15] fp32 (sampled targets)")
+    pos, mass, spec = inputs.make("clumpy4m")
+    g = (len(pos) + 63) // 64
+    thg = np.random.default_rng(41).uniform(0.2, 1.15, g).astype(np.float32)
+    tg = inputs.sample_targets(len(pos), 2048, spec["seed"] + 200)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp32", 0.5, spec["eps"], targets=tg, theta_group=thg)
+    check_forces(acc, w["acc"], w["amag"], F32_TOL, "clumpy4m per-group", log=say)
+    assert pot_err(pot, w["pot"]).max() <= F32_TOL
+
+
+def test_fp64_walk_full_size(bh):
+    """The FP64 walk (the accuracy reference of the Plummer sweep) at N = 1,048,576, theta = 0.5:
+    counts, hashes and forces of 2048 sampled targets against the oracle at 1e-12."""
+    say("[full] plummer1m fp64 theta=0.5 (sampled targets)")
+    pos, mass, spec = inputs.make("plummer1m")
+    tg = inputs.sample_targets(len(pos), 2048, spec["seed"] + 300)
+    acc, pot, w = _walk_compare(bh, pos, mass, "fp64", 0.5, spec["eps"], targets=tg)
+    check_forces(acc, w["acc"], w["amag"], F64_TOL, "plummer1m fp64", log=say)
+    assert pot_err(pot, w["pot"]).max() <= F64_TOL

@@ -6,6 +6,8 @@ same layers, central finite differences of the loss, torch's Adam, an
 analytic lattice for the geometric features, and a brute-force search for the
 containing cell.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -165,3 +167,68 @@ def test_group_rms_definition():
     r = learn.group_rms(acc, ref, perm)
     assert r.shape == (4,)
     np.testing.assert_allclose(r, 1e-3, rtol=1e-9)
+
+
+def test_group_rms_skips_zero_reference():
+    # a particle with a_ref = 0 has no relative error: left out of its group's mean
+    n = 130
+    rng = np.random.default_rng(8)
+    ref = rng.normal(size=(n, 3))
+    acc = ref * (1 + 2e-3)                     # relative error exactly 2e-3 (up to rounding)
+    ref[5] = 0.0
+    acc[5] = 1.0
+    ref[64:128] = 0.0                          # a whole group of zero references
+    perm = np.arange(n)
+    r = learn.group_rms(acc, ref, perm)
+    np.testing.assert_allclose(r[[0, 2]], 2e-3, rtol=1e-9)
+    assert r[1] == 0.0 and np.all(np.isfinite(r))
+
+
+# ------------------------------------------------ label allocation (host, learn.allocate)
+def _alloc_tables(seed, K=4, G=6):
+    rng = np.random.default_rng(seed)
+    # error falls and cost rises toward small theta (grid index 0), with noise
+    R = np.sort(rng.uniform(1e-4, 4e-3, (K, G)), axis=0)
+    C = np.sort(rng.uniform(10, 200, (K, G)), axis=0)[::-1].copy()
+    n_g = rng.integers(1, 65, G).astype(np.float64)
+    return R, C, n_g
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("target", [8e-4, 1.5e-3, 2.5e-3])
+def test_allocate_against_enumeration(seed, target):
+    """learn.allocate picks a Lagrangian point of min C s.t. error <= target: its error is within
+    the target, and no choice of grid index per group (all K^G enumerated) with an error no larger
+    has a lower total cost."""
+    import itertools
+    from paper_1112_4539_amd import learn as plearn
+    R, C, n_g = _alloc_tables(seed)
+    K, G = R.shape
+    k = plearn.allocate(R, C, n_g, target)
+    N = n_g.sum()
+    err = lambda ks: math.sqrt(sum(n_g[g] * R[ks[g], g] ** 2 for g in range(G)) / N)
+    cost = lambda ks: sum(C[ks[g], g] for g in range(G))
+    e_k, c_k = err(k), cost(k)
+    feasible = [ks for ks in itertools.product(range(K), repeat=G) if err(ks) <= target]
+    if not feasible:                           # nothing meets the target: the most accurate choice
+        assert np.all(k == np.argmin(C + 1e40 * n_g * R * R, axis=0))
+        return
+    assert e_k <= target * (1 + 1e-12)
+    best_at_ek = min(cost(ks) for ks in itertools.product(range(K), repeat=G) if err(ks) <= e_k * (1 + 1e-12))
+    assert c_k <= best_at_ek * (1 + 1e-12)
+
+
+def test_allocate_ignores_non_finite_groups():
+    from paper_1112_4539_amd import learn as plearn
+    R, C, n_g = _alloc_tables(3, K=5, G=8)
+    k0 = plearn.allocate(R, C, n_g, 2e-3)
+    R2 = np.hstack([R, np.full((5, 1), np.inf)])
+    C2 = np.hstack([C, np.full((5, 1), 50.0)])
+    k2 = plearn.allocate(R2, C2, np.append(n_g, 64.0), 2e-3)
+    assert k2[-1] == 0
+    np.testing.assert_array_equal(k2[:-1], k0)
+    # a single non-finite entry is avoided, the rest of its column still usable
+    R3 = R.copy()
+    R3[4, 2] = np.nan
+    k3 = plearn.allocate(R3, C, n_g, 2e-3)
+    assert k3[2] != 4 and np.all(k3 >= 0)

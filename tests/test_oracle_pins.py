@@ -386,3 +386,58 @@ def test_walk_error_vs_theta_and_paper_table(oracle_mod):
     assert all(b > a for a, b in zip(errs, errs[1:]))
     slope = np.polyfit(np.log(tab[:, 0]), np.log(errs), 1)[0]
     assert 1.5 < slope < 3.5
+
+
+# ------------------------------------------ A_i = sum_j |f_ij| (cancellation floor)
+def test_amag_two_body_equals_force(oracle_mod):
+    # one term: the sum of term magnitudes is the force itself, |a| = m r / (r^2 + eps^2)^(3/2)
+    pos = np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 2.0]])
+    acc, _, amag = oracle_mod.direct(pos, np.array([1.0, 0.75]), 4.0)
+    assert abs(amag[0] - 0.75 * 3.0 / 125.0) <= 4 * np.spacing(0.018)
+    assert abs(amag[1] - 1.0 * 3.0 / 125.0) <= 4 * np.spacing(0.024)
+    np.testing.assert_allclose(amag, np.linalg.norm(acc, axis=1), rtol=4e-16)
+
+
+def test_amag_collinear_sources_equals_force(oracle_mod):
+    # every source on the +x ray from the target: all terms point the same way, so
+    # sum |f| = |sum f|, while a term that forgot |dx| or used the softened distance would not match
+    xs = np.array([0.0, 0.3, 1.0, 2.5, 4.0, 7.25])
+    pos = np.zeros((len(xs), 3))
+    pos[:, 0] = xs
+    mass = np.array([1.0, 0.5, 2.0, 0.25, 3.0, 1.5])
+    eps = 0.2
+    acc, _, amag = oracle_mod.direct(pos, mass, eps, targets=np.array([0]))
+    ref = math.fsum(float(m) * float(x) / (float(x) ** 2 + eps * eps) ** 1.5 for m, x in zip(mass[1:], xs[1:]))
+    assert abs(amag[0] - ref) <= 1e-15 * ref
+    assert abs(acc[0, 0] - ref) <= 1e-15 * ref and acc[0, 1] == 0.0 and acc[0, 2] == 0.0
+
+
+def test_amag_symmetric_pair_cancels(oracle_mod):
+    # sources at +-r e_x: the force cancels exactly, A = 2 m r / (r^2 + eps^2)^(3/2)
+    r, m, eps = 0.75, 0.4, 0.5
+    pos = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0], [-r, 0.0, 0.0]])
+    acc, _, amag = oracle_mod.direct(pos, np.array([1.0, m, m]), eps, targets=np.array([0]))
+    assert np.all(acc[0] == 0.0)
+    _, p = _closed_pair((0.0, 0.0, 0.0), (r, 0.0, 0.0), m, eps)   # p = -m / sqrt(r^2 + eps^2)
+    ref = 2.0 * (-p) * r / (r * r + eps * eps)
+    assert abs(amag[0] - ref) <= 4 * np.spacing(ref)
+
+
+def test_amag_of_walk_cell_and_limit(oracle_mod):
+    # theta -> 0: the walk's A equals the direct sum's (same terms, another order)
+    pos, mass = inputs.plummer(1500, 13)
+    w = oracle_mod.Tree(pos, mass).walk(1e-6, 0.01)
+    _, _, amag = oracle_mod.direct(pos, mass, 0.01)
+    np.testing.assert_allclose(w["amag"], amag, rtol=1e-13)
+    # a far target sees a compact cluster as one cell term: A = M d / (d^2 + eps^2)^(3/2), d to the
+    # cluster's centre of mass
+    rng = np.random.default_rng(3)
+    cl = rng.random((50, 3)) * 1e-3
+    pos = np.vstack([cl, [[10.0, 0.0, 0.0]]])
+    mass = np.full(51, 0.02)
+    T = oracle_mod.Tree(pos, mass)
+    w = T.walk(0.5, 0.05, targets=np.array([50]))
+    assert w["n_pc"][0] == 1 and w["n_pp"][0] == 0
+    com = (mass[:50, None] * cl).sum(0) / mass[:50].sum()
+    d = np.linalg.norm(com - pos[50])
+    assert abs(w["amag"][0] - 1.0 * d / (d * d + 0.05 ** 2) ** 1.5) <= 1e-12

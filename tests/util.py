@@ -23,6 +23,31 @@ def force_err(acc, acc_ref, amag, kappa_max=1e3):
     return np.linalg.norm(acc - acc_ref, axis=1) / den
 
 
+def floor_share(acc_ref, amag, kappa_max=1e3):
+    """Share of particles whose error denominator is the cancellation floor A_i / kappa_max
+    rather than |a_ref_i| (their force cancels by more than kappa_max)."""
+    a = np.linalg.norm(widen(acc_ref), axis=1)
+    if len(a) == 0:
+        return 0.0
+    return float(np.mean(widen(amag) / kappa_max > a))
+
+
+def check_forces(acc, acc_ref, amag, tol, label="", max_floor_share=1e-3, log=print):
+    """Assert the per-particle force errors (force_err) are within tol, reporting the worst error,
+    the 99th percentile and the share of particles where the cancellation floor sets the
+    denominator; that share must stay at most max_floor_share, so that the floor cannot hide a
+    loose comparison.  Returns the errors."""
+    e = force_err(acc, acc_ref, amag)
+    share = floor_share(acc_ref, amag)
+    kap = widen(amag) / np.maximum(np.linalg.norm(widen(acc_ref), axis=1), 1e-300)
+    if len(e):
+        log(f"  {label} max err {e.max():.3e}  p99 {np.quantile(e, 0.99):.3e}  floor share {share:.2e}  "
+            f"max A/|a| {kap.max():.1f}")
+        assert e.max() <= tol, f"{label}: max force error {e.max():.3e} > {tol:g}"
+    assert share <= max_floor_share, f"{label}: cancellation floor used for {share:.2e} of the particles"
+    return e
+
+
 def pot_err(pot, pot_ref):
     """Relative potential error (absolute where the reference is exactly 0)."""
     pot = widen(pot)
