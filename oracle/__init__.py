@@ -11,7 +11,10 @@ this module only loads it and marshals numpy arrays.  Definitions followed:
   acceleration is attractive, the potential is the physical ``-sum m/r``.
 * ``Tree``        -- Sec. 4.1 recursive oct-tree on the 2^21 grid of the root
   cube, compressed, with the Sec. 4.4 monopole moments and Eq. (2) cell sizes.
-* ``Tree.walk``   -- Fig. 3 recursive walk with the opening test of Eq. (2)/(3).
+* ``Tree.walk``   -- Fig. 3 recursive walk with the opening test of Eq. (2)/(3);
+  ``order=2`` adds the quadrupole cell term (Sec. 4.1, Sec. 7: higher moments).
+* ``Tree.neighbours`` -- Sec. 4.3, Fig. 4: the general tree walk as a neighbour
+  search with the SPH density as its per-neighbour work.
 * ``rms_rel_err`` / ``mean_rel_err`` -- Sec. 5, Eq. (4) and its RMS form.
 """
 from __future__ import annotations
@@ -62,8 +65,18 @@ def _load():
     lib.orc_tree_cube.restype = None
     lib.orc_tree_export.argtypes = [P] * 12
     lib.orc_tree_export.restype = None
-    lib.orc_walk.argtypes = [P, P, i64, d, P, d, P, P, P, P, P, P, P, i64]
+    lib.orc_walk.argtypes = [P, P, i64, d, P, d, ctypes.c_int, P, P, P, P, P, P, P, i64]
     lib.orc_walk.restype = ctypes.c_int
+    lib.orc_tree_quad.argtypes = [P, P]
+    lib.orc_tree_quad.restype = None
+    lib.orc_cell_term.argtypes = [P, P, d, P, d, ctypes.c_int, P, P]
+    lib.orc_cell_term.restype = None
+    lib.orc_sph_kernel.argtypes = [d, d]
+    lib.orc_sph_kernel.restype = d
+    lib.orc_neighbours.argtypes = [P, P, i64, d, P, P, P, i64, P]
+    lib.orc_neighbours.restype = ctypes.c_int
+    lib.orc_neighbours_brute.argtypes = [P, P, i64, P, i64, d, P, P]
+    lib.orc_neighbours_brute.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -147,8 +160,18 @@ class Tree:
             _load().orc_tree_free(h)
             self._h = None
 
-    def walk(self, theta, eps, targets=None, theta_per_target=None, maxlen=0):
+    @property
+    def B(self):
+        """Second moments [n_nodes, 6] (xx xy xz yy yz zz) of every node about its centre of mass."""
+        out = np.zeros((self.n_nodes, 6))
+        _load().orc_tree_quad(self._h, _ptr(out))
+        return out
+
+    def walk(self, theta, eps, targets=None, theta_per_target=None, maxlen=0, order=1):
         """Fig. 3 walk for ``targets`` (original indices; all if None).
+
+        ``order`` 1: monopole cell terms (Eq. (1) with the cell's mass at its centre of
+        mass); 2: the second-order expansion of the softened cell potential (quadrupole).
 
         Returns a dict with ``acc [nt,3]``, ``pot``, ``amag``, ``n_pp``, ``n_pc``,
         ``hash`` (uint64 ordered-list hash) and, if ``maxlen`` > 0, ``lists``
@@ -169,7 +192,7 @@ class Tree:
         lists = None
         if maxlen > 0:
             lists = np.full((nt, maxlen), -1, np.int64)
-        rc = lib.orc_walk(self._h, _ptr(tg), nt, float(theta), _ptr(tpt), float(eps),
+        rc = lib.orc_walk(self._h, _ptr(tg), nt, float(theta), _ptr(tpt), float(eps), int(order),
                           _ptr(out["acc"]), _ptr(out["pot"]), _ptr(out["amag"]),
                           _ptr(out["n_pp"]), _ptr(out["n_pc"]), _ptr(out["hash"]),
                           _ptr(lists), int(maxlen))
@@ -178,6 +201,57 @@ class Tree:
         if lists is not None:
             out["lists"] = lists
         return out
+
+
+def sph_kernel(r, h):
+    """M4 cubic spline W(r, h) of compact support 2h (three dimensions)."""
+    return float(_load().orc_sph_kernel(float(r), float(h)))
+
+
+def neighbours_brute(pos, mass, radius, targets=None):
+    """Brute force over all pairs: (count [nt], rho [nt]) of the neighbours within ``radius``."""
+    lib = _load()
+    pos = _as_pos(pos)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = pos.shape[0] if tg is None else tg.shape[0]
+    cnt = np.zeros(nt, np.int64)
+    rho = np.zeros(nt)
+    if lib.orc_neighbours_brute(_ptr(pos), _ptr(mass), pos.shape[0], _ptr(tg), nt, float(radius), _ptr(cnt),
+                                _ptr(rho)) != 0:
+        raise ValueError("orc_neighbours_brute rejected its arguments")
+    return cnt, rho
+
+
+def cell_term(xi, com, M, B, eps, order=2):
+    """One particle-cell term at target xi of a cell with mass M, centre of mass com and second
+    moments B (xx xy xz yy yz zz); returns (acc [3], pot)."""
+    xi = np.ascontiguousarray(xi, np.float64)
+    com = np.ascontiguousarray(com, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    acc = np.zeros(3)
+    pot = np.zeros(1)
+    _load().orc_cell_term(_ptr(xi), _ptr(com), float(M), _ptr(B), float(eps), int(order), _ptr(acc), _ptr(pot))
+    return acc, float(pot[0])
+
+
+def _tree_neighbours(self, radius, targets=None, maxlen=0):
+    """General tree walk of Fig. 4 as a neighbour search: per target the count of particles within
+    ``radius``, their ordered hash (walk order), optional lists and the SPH density."""
+    lib = _load()
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = self.n if tg is None else tg.shape[0]
+    out = dict(count=np.zeros(nt, np.int64), hash=np.zeros(nt, np.uint64), rho=np.zeros(nt))
+    lists = np.full((nt, maxlen), -1, np.int64) if maxlen > 0 else None
+    if lib.orc_neighbours(self._h, _ptr(tg), nt, float(radius), _ptr(out["count"]), _ptr(out["hash"]),
+                          _ptr(lists), int(maxlen), _ptr(out["rho"])) != 0:
+        raise ValueError("orc_neighbours rejected its arguments")
+    if lists is not None:
+        out["lists"] = lists
+    return out
+
+
+Tree.neighbours = _tree_neighbours
 
 
 def rms_rel_err(a, a_ref):

@@ -39,6 +39,20 @@
  *                           preorder, children in octant order, so more(c) = c+1
  *                           and next(c) = the first node after c's subtree.
  *   error statistics ...... Sec. 5, Eq. (4) (mean relative error) and its RMS form.
+ *   neighbour search ...... Sec. 4.3, Fig. 4 (general tree walk): proc_particle
+ *                           records a particle within the search radius,
+ *                           distance_test skips a cell whose cube lies wholly
+ *                           outside the search ball, proc_cell does nothing.  The
+ *                           per-neighbour work here is the SPH density sum with
+ *                           the M4 cubic spline kernel (Monaghan & Lattanzio 1985).
+ *   quadrupole cell term .. Sec. 4.1 allows any higher moment in the particle-cell
+ *                           term and Sec. 7 names higher multipoles as the next
+ *                           step.  Order 2 here is the second-order Taylor
+ *                           expansion, about the cell's centre of mass, of the
+ *                           softened potential of Eq. (1) summed over the cell's
+ *                           particles; it needs the cell's second moments
+ *                           B_ab = sum_j m_j y_a y_b, y = x_j - com (definition
+ *                           evaluated directly over the cell's particles).
  */
 #include <math.h>
 #include <stdint.h>
@@ -73,6 +87,51 @@ static void orc_pair(const double *xi, const double *xj, double mj, double eps2,
   acc[2] += mr3 * dz;
   *pot -= mj * rinv;
   *amag += fabs(mr3) * sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* Particle-cell term to second order: the Taylor expansion about the centre of
+ * mass `com` of sum_j m_j g(x_i - x_j), g(r) = -(|r|^2 + eps^2)^(-1/2), over
+ * the cell's particles, with M = sum m_j, the first moment zero about com, and
+ * second moments B (xx xy xz yy yz zz), T = trace B.  With d = com - x_i,
+ * rho^2 = |d|^2 + eps^2, and dBd = d.B.d:
+ *   pot = -M/rho + (T/rho^3 - 3 dBd/rho^5) / 2
+ *   acc = M d/rho^3 - 3 (B d)/rho^5 + (15/2 dBd/rho^7 - 3/2 T/rho^5) d
+ * (the second derivatives of g give delta_ab rho^-3 - 3 r_a r_b rho^-5; the
+ * acceleration is minus the gradient of pot in x_i).  amag gets |acc|. */
+static void orc_pair_quad(const double *xi, const double *cm, double M, const double *B, double eps2,
+                          double *acc, double *pot, double *amag) {
+  double d[3] = {cm[0] - xi[0], cm[1] - xi[1], cm[2] - xi[2]};
+  double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+  if (r2 == 0.0) return;
+  double ri = 1.0 / sqrt(r2);
+  double ri2 = ri * ri;
+  double ri3 = ri * ri2;
+  double ri5 = ri3 * ri2;
+  double ri7 = ri5 * ri2;
+  double Bd[3] = {B[0] * d[0] + B[1] * d[1] + B[2] * d[2],
+                  B[1] * d[0] + B[3] * d[1] + B[4] * d[2],
+                  B[2] * d[0] + B[4] * d[1] + B[5] * d[2]};
+  double dBd = d[0] * Bd[0] + d[1] * Bd[1] + d[2] * Bd[2];
+  double T = B[0] + B[3] + B[5];
+  double f[3];
+  for (int k = 0; k < 3; ++k)
+    f[k] = M * ri3 * d[k] - 3.0 * ri5 * Bd[k] + (7.5 * dBd * ri7 - 1.5 * T * ri5) * d[k];
+  acc[0] += f[0];
+  acc[1] += f[1];
+  acc[2] += f[2];
+  *pot += -M * ri + 0.5 * (T * ri3 - 3.0 * dBd * ri5);
+  *amag += sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+}
+
+/* One cell term of order 2 for a given centre of mass, mass and second moments
+ * (no tree): used to test the expansion against the exact sum it approximates. */
+void orc_cell_term(const double *xi, const double *cm, double M, const double *B, double eps, int order,
+                   double *acc, double *pot) {
+  double a[3] = {0, 0, 0}, p = 0, am = 0;
+  if (order == 2) orc_pair_quad(xi, cm, M, B, eps * eps, a, &p, &am);
+  else orc_pair(xi, cm, M, eps * eps, a, &p, &am);
+  acc[0] = a[0]; acc[1] = a[1]; acc[2] = a[2];
+  *pot = p;
 }
 
 /* Direct sum over all j != i (ascending original index) for each target.
@@ -115,6 +174,7 @@ typedef struct {
   int8_t *leaf;
   int64_t *cell;             /* [node][3] integer cell coordinates at its level */
   double *com, *Mx;          /* [node][3] */
+  double *B;                 /* [node][6] second moments about the centre of mass: xx xy xz yy yz zz */
   double *M, *s, *l;
   /* particle order */
   int64_t *perm;             /* sorted position -> original index (leaf order) */
@@ -129,7 +189,7 @@ static int orc_grow(otree *t) {
 #define GROW(f, T, k) do { void *p_ = realloc(t->f, (size_t)cap * (k) * sizeof(T)); if (!p_) return -1; t->f = (T *)p_; } while (0)
   GROW(level, int32_t, 1); GROW(first, int32_t, 1); GROW(count, int32_t, 1);
   GROW(next, int32_t, 1); GROW(leaf, int8_t, 1); GROW(cell, int64_t, 3);
-  GROW(com, double, 3); GROW(Mx, double, 3); GROW(M, double, 1);
+  GROW(com, double, 3); GROW(Mx, double, 3); GROW(M, double, 1); GROW(B, double, 6);
   GROW(s, double, 1); GROW(l, double, 1);
 #undef GROW
   t->cap = cap;
@@ -197,7 +257,7 @@ static int64_t orc_build_rec(otree *t, int level, int64_t cx, int64_t cy, int64_
 void orc_tree_free(otree *t) {
   if (!t) return;
   free(t->q); free(t->level); free(t->first); free(t->count); free(t->next);
-  free(t->leaf); free(t->cell); free(t->com); free(t->Mx); free(t->M);
+  free(t->leaf); free(t->cell); free(t->com); free(t->Mx); free(t->M); free(t->B);
   free(t->s); free(t->l); free(t->perm); free(t->rank); free(t->tmp);
   free(t);
 }
@@ -287,7 +347,30 @@ otree *orc_tree_build(const double *pos, const double *mass, int64_t n) {
       t->s[c] = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
     }
   }
+  /* Second moments about each node's centre of mass, straight from the
+   * definition: B_ab = sum over the node's particles of m (x_a - com_a)(x_b - com_b),
+   * particles in sorted order.  (A one-particle leaf has B = 0 exactly.) */
+  int64_t cc;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (cc = 0; cc < t->n_nodes; ++cc) {
+    double b[6] = {0, 0, 0, 0, 0, 0};
+    const double *cm = t->com + 3 * cc;
+    for (int64_t k = t->first[cc]; k < (int64_t)t->first[cc] + t->count[cc]; ++k) {
+      int64_t j = t->perm[k];
+      double y0 = pos[3 * j] - cm[0], y1 = pos[3 * j + 1] - cm[1], y2 = pos[3 * j + 2] - cm[2];
+      double m = mass[j];
+      b[0] += m * y0 * y0; b[1] += m * y0 * y1; b[2] += m * y0 * y2;
+      b[3] += m * y1 * y1; b[4] += m * y1 * y2; b[5] += m * y2 * y2;
+    }
+    if (t->leaf[cc] && t->count[cc] == 1) for (int a = 0; a < 6; ++a) b[a] = 0.0;
+    for (int a = 0; a < 6; ++a) t->B[6 * cc + a] = b[a];
+  }
   return t;
+}
+
+/* Second moments [n_nodes][6] (xx xy xz yy yz zz) about each node's centre of mass. */
+void orc_tree_quad(const otree *t, double *B) {
+  memcpy(B, t->B, (size_t)t->n_nodes * 6 * sizeof(double));
 }
 
 int64_t orc_tree_nodes(const otree *t) { return t ? t->n_nodes : -1; }
@@ -334,6 +417,7 @@ typedef struct {
   int64_t ri;          /* its sorted position */
   const double *xi;
   double inv_theta, eps2;
+  int order;           /* 1: monopole cell terms (Eq. (1)), 2: with the quadrupole correction */
   double a[3], p, amag;
   int64_t n_pp, n_pc;
   uint64_t hash;
@@ -369,7 +453,10 @@ static void orc_treewalk(orc_walker *w, int64_t c) {
     double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
     double u = fma(t->l[c], w->inv_theta, t->s[c]);  /* l/theta + s */
     if (d2 > u * u) {
-      orc_pair(w->xi, cm, t->M[c], w->eps2, w->a, &w->p, &w->amag);
+      if (w->order == 2)
+        orc_pair_quad(w->xi, cm, t->M[c], t->B + 6 * c, w->eps2, w->a, &w->p, &w->amag);
+      else
+        orc_pair(w->xi, cm, t->M[c], w->eps2, w->a, &w->p, &w->amag);
       w->n_pc++;
       orc_record(w, ((uint64_t)c << 1) | 1u);
       return;
@@ -379,14 +466,16 @@ static void orc_treewalk(orc_walker *w, int64_t c) {
 }
 
 /* Walk the tree for each target (original indices; NULL = all n in order).
- * theta_per_target (nt values, may be NULL) overrides theta.  Outputs per
+ * theta_per_target (nt values, may be NULL) overrides theta.  order 1 uses
+ * monopole cell terms, order 2 adds the quadrupole correction (the opening
+ * test and so the lists are the same for both).  Outputs per
  * target: acc [3], pot, amag (sum of |term|), n_pp, n_pc, hash; any may be
  * NULL.  lists (optional) is [nt][maxlen] of int64 words (truncated). */
 int orc_walk(const otree *t, const int64_t *targets, int64_t nt, double theta,
-             const double *theta_per_target, double eps, double *acc, double *pot,
+             const double *theta_per_target, double eps, int order, double *acc, double *pot,
              double *amag, int64_t *n_pp, int64_t *n_pc, uint64_t *hash,
              int64_t *lists, int64_t maxlen) {
-  if (!t || nt < 0 || eps < 0) return -1;
+  if (!t || nt < 0 || eps < 0 || (order != 1 && order != 2)) return -1;
   int64_t k;
   int bad = 0;
 #pragma omp parallel for schedule(dynamic, 8) reduction(| : bad)
@@ -401,6 +490,7 @@ int orc_walk(const otree *t, const int64_t *targets, int64_t nt, double theta,
     double th = theta_per_target ? theta_per_target[k] : theta;
     w.inv_theta = 1.0 / th;
     w.eps2 = eps * eps;
+    w.order = order;
     w.hash = ORC_FNV_OFFSET;
     w.list = lists ? lists + k * maxlen : NULL;
     w.maxlen = maxlen;
@@ -413,6 +503,131 @@ int orc_walk(const otree *t, const int64_t *targets, int64_t nt, double theta,
     if (hash) hash[k] = w.hash;
   }
   return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Neighbour search: the general tree walk of Fig. 4.                        */
+/* ------------------------------------------------------------------------- */
+
+/* M4 cubic spline of compact support 2h in three dimensions (Monaghan &
+ * Lattanzio 1985): W(r, h) = 1/(pi h^3) * {1 - 3/2 q^2 + 3/4 q^3 for q < 1,
+ * (2 - q)^3 / 4 for 1 <= q < 2, 0 beyond}, q = r/h. */
+double orc_sph_kernel(double r, double h) {
+  double q = r / h;
+  double sig = 1.0 / (M_PI * h * h * h);
+  if (q < 1.0) return sig * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
+  if (q < 2.0) { double u = 2.0 - q; return sig * 0.25 * u * u * u; }
+  return 0.0;
+}
+
+typedef struct {
+  const otree *t;
+  int64_t i;
+  const double *xi;
+  double r2;           /* squared search radius */
+  double h;            /* kernel scale: radius / 2 */
+  double rho;
+  int64_t count;
+  uint64_t hash;
+  int64_t *list, maxlen, len;
+} orc_nbr;
+
+/* proc_particle: j (original index) is a neighbour of i iff j != i and
+ * |x_j - x_i|^2 < radius^2 (squared distance as fma(dz,dz,fma(dy,dy,dx*dx))). */
+static void orc_nbr_particle(orc_nbr *w, int64_t j) {
+  if (j == w->i) return;
+  const double *xj = w->t->pos + 3 * j;
+  double dx = xj[0] - w->xi[0], dy = xj[1] - w->xi[1], dz = xj[2] - w->xi[2];
+  double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  if (!(d2 < w->r2)) return;
+  w->count++;
+  w->hash = (w->hash ^ ((uint64_t)j << 1)) * ORC_FNV_PRIME;
+  if (w->list && w->len < w->maxlen) w->list[w->len] = (int64_t)j;
+  w->len++;
+  w->rho += w->t->mass[j] * orc_sph_kernel(sqrt(d2), w->h);
+}
+
+/* distance_test: the cell's cube [lo + cell l, lo + (cell + 1) l) cannot hold a
+ * point within the radius iff its nearest point to x_i is at least the radius
+ * away. */
+static int orc_cell_far(const orc_nbr *w, int64_t c) {
+  const otree *t = w->t;
+  double l = t->l[c], d2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double lo = t->lo[d] + (double)t->cell[3 * c + d] * l, hi = lo + l, x = w->xi[d], e = 0.0;
+    if (x < lo) e = lo - x;
+    else if (x > hi) e = x - hi;
+    d2 += e * e;
+  }
+  return d2 >= w->r2;
+}
+
+static void orc_nbrwalk(orc_nbr *w, int64_t c) {
+  const otree *t = w->t;
+  if (t->leaf[c]) {
+    for (int64_t k = t->first[c]; k < (int64_t)t->first[c] + t->count[c]; ++k) orc_nbr_particle(w, t->perm[k]);
+    return;
+  }
+  if (orc_cell_far(w, c)) return;
+  for (int64_t ch = c + 1; ch < t->next[c]; ch = t->next[ch]) orc_nbrwalk(w, ch);
+}
+
+/* Neighbours within `radius` of each target (original indices; NULL = all):
+ * count, ordered hash of the neighbours' original indices j (word j << 1, the
+ * walk's depth-first order, FNV-1a as for interaction lists), optional lists
+ * [nt][maxlen], and the SPH density rho_i = m_i W(0, h) + sum_j m_j W(r_ij, h)
+ * with h = radius / 2 (any output may be NULL). */
+int orc_neighbours(const otree *t, const int64_t *targets, int64_t nt, double radius, int64_t *count,
+                   uint64_t *hash, int64_t *lists, int64_t maxlen, double *rho) {
+  if (!t || nt < 0 || !(radius > 0.0)) return -1;
+  int64_t k;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+  for (k = 0; k < nt; ++k) {
+    orc_nbr w;
+    memset(&w, 0, sizeof w);
+    w.t = t;
+    w.i = targets ? targets[k] : k;
+    if (w.i < 0 || w.i >= t->n) { bad = 1; continue; }
+    w.xi = t->pos + 3 * w.i;
+    w.r2 = radius * radius;
+    w.h = 0.5 * radius;
+    w.rho = t->mass[w.i] * orc_sph_kernel(0.0, w.h);
+    w.hash = ORC_FNV_OFFSET;
+    w.list = lists ? lists + k * maxlen : NULL;
+    w.maxlen = maxlen;
+    if (t->n_nodes > 0) orc_nbrwalk(&w, 0);
+    if (count) count[k] = w.count;
+    if (hash) hash[k] = w.hash;
+    if (rho) rho[k] = w.rho;
+  }
+  return bad ? -1 : 0;
+}
+
+/* Brute force over all pairs: neighbour counts and the density, for the pins. */
+int orc_neighbours_brute(const double *pos, const double *mass, int64_t n, const int64_t *targets, int64_t nt,
+                         double radius, int64_t *count, double *rho) {
+  if (n < 0 || nt < 0 || !(radius > 0.0)) return -1;
+  double r2 = radius * radius, h = 0.5 * radius;
+  int64_t k;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (k = 0; k < nt; ++k) {
+    int64_t i = targets ? targets[k] : k;
+    int64_t cnt = 0;
+    double rh = mass[i] * orc_sph_kernel(0.0, h);
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double dx = pos[3 * j] - pos[3 * i], dy = pos[3 * j + 1] - pos[3 * i + 1], dz = pos[3 * j + 2] - pos[3 * i + 2];
+      double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+      if (d2 < r2) {
+        ++cnt;
+        rh += mass[j] * orc_sph_kernel(sqrt(d2), h);
+      }
+    }
+    if (count) count[k] = cnt;
+    if (rho) rho[k] = rh;
+  }
+  return 0;
 }
 
 int orc_num_threads(void) {
