@@ -120,6 +120,27 @@ BH_API int bh_forces(const bh_tree *t, double theta, double eps, void *acc, void
 BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double eps, void *acc, void *pot,
                     void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): build + forces in one call
+ * for up to BH_NOALLOC_MAX_N particles, with no workspace argument.  Every
+ * intermediate array lives in one static device array of the library,
+ * BH_NOALLOC_SCRATCH_BYTES per GPU (allocated when the library's code is
+ * loaded on a GPU, held until the process ends).  The call allocates no
+ * device or host memory.
+ *   pos [n][3], mass [n], acc [n][3], pot [n]: device, caller order, precision
+ *   prec, as for bh_build_tree + bh_forces, whose results it reproduces bit for
+ *   bit (default walk shape).  theta, eps: as for bh_forces.
+ *   The work runs on `stream` of the current device.
+ * Errors: BH_EINVAL for n outside [0, BH_NOALLOC_MAX_N] or any argument
+ * bh_build_tree / bh_forces reject.  Every call on a GPU shares that GPU's
+ * array, which keeps the last call's contents (each call rewrites what it
+ * reads): calls whose GPU work overlaps on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+#define BH_NOALLOC_MAX_N 65536
+#define BH_NOALLOC_SCRATCH_BYTES (48 << 20)
+BH_API int bh_forces_noalloc(const void *pos, const void *mass, int64_t n, int prec, double theta, double eps,
+                             void *acc, void *pot, void *stream);
+
 /* The walk of bh_forces / bh_forces_theta (theta_group may be NULL) that also
  * records, per particle in caller order, counts [n][2] = (particle terms, cell
  * terms) and hash [n] = ordered-list hash: h = (h xor w) * 1099511628211 from

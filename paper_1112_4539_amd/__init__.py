@@ -14,7 +14,7 @@ import os
 
 import torch
 
-__all__ = ["Tree", "Forest", "Graph", "build_tree", "build_forest", "direct", "workspace_bytes",
+__all__ = ["Tree", "Forest", "Graph", "build_tree", "build_forest", "direct", "forces_noalloc", "workspace_bytes",
            "forest_workspace_bytes", "load", "THETA_MAX", "BHError", "FP32", "FP64", "WalkConfig"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -63,6 +63,7 @@ def load():
         "bh_tree_stats": ([P, P, P, P, P], i32),
         "bh_forces": ([P, d, d, P, P, P], i32),
         "bh_forces_theta": ([P, P, d, P, P, P], i32),
+        "bh_forces_noalloc": ([P, P, i64, i32, d, d, P, P, P], i32),
         "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P, P], i32),
         "bh_tree_export": ([P, P, P, P], i32),
         "bh_set_walk_config": ([P, i32, i32, i32, i32, i32, i32], i32),
@@ -400,6 +401,24 @@ def build_tree(pos, mass, workspace=None):
 def build_forest(pos, mass, offsets, workspace=None):
     """One tree per cluster [offsets[k], offsets[k+1]) in one build (``bh_build_forest``)."""
     return Tree(pos, mass, workspace, offsets=offsets)
+
+
+NOALLOC_MAX_N = 65536
+
+
+def forces_noalloc(pos, mass, theta, eps, acc, pot):
+    """Build + forces with the library's static scratch array (``bh_forces_noalloc``): no device
+    memory is allocated, by the library or here; acc [n,3] and pot [n] are the caller's."""
+    lib = load()
+    prec = _prec_of(pos.dtype)
+    n = int(pos.shape[0])
+    for t, shape in ((pos, (n, 3)), (mass, (n,)), (acc, (n, 3)), (pot, (n,))):
+        if t.dtype != pos.dtype or tuple(t.shape) != shape or not t.is_contiguous() or t.device != pos.device:
+            raise ValueError("pos/acc must be [n,3] and mass/pot [n], contiguous, one dtype and device")
+    with torch.cuda.device(pos.device):
+        _check(lib.bh_forces_noalloc(_ptr(pos), _ptr(mass), n, prec, float(theta), float(eps), _ptr(acc),
+                                     _ptr(pot), _stream(pos.device)))
+    return acc, pot
 
 
 def direct(pos, mass, eps, targets=None):

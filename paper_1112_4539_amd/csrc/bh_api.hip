@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/bh.h"
@@ -247,6 +248,35 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   return BH_OK;
 }
 
+// ---- the allocation-free entry point (bh_forces_noalloc)
+// Its workspace is this file-scope device array: each GPU the library runs on
+// holds its own copy, allocated when the code object is loaded there and kept
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not a device address: the device address comes from hipGetSymbolAddress,
+// once per device with that device current, and is the only one ever handed
+// to kernels.
+static_assert(BH_NOALLOC_SCRATCH_BYTES % kAlign == 0, "scratch size must keep the workspace alignment");
+static __device__ __align__(256) unsigned char scratch[BH_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;                 // guards the two tables below (host state only)
+void* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+bh_tree g_noalloc_tree[kMaxDevices];     // host handle of the tree built in `scratch`, per device
+
+// Device address of this device's scratch array (looked up on the device's first call).
+// The caller holds g_noalloc_mu.
+int scratch_address(int dev, void** out) {
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "locating the static scratch array");
+    if (!p || !aligned(p, kAlign)) return fail(BH_EHIP, "the static scratch array is not 256-byte aligned");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return BH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -335,6 +365,48 @@ int bh_forces_theta(const bh_tree* t, const float* theta_group, double eps, void
   if (!theta_group) return fail(BH_EINVAL, "theta_group must not be null");
   return run_walk(t, 0.0, theta_group, eps, acc, pot, bh::kWalkForces, nullptr, nullptr, nullptr, 0,
                   nullptr, static_cast<hipStream_t>(stream));
+}
+
+int bh_forces_noalloc(const void* pos, const void* mass, int64_t n, int prec, double theta, double eps, void* acc,
+                      void* pot, void* stream) {
+  if (n < 0 || n > BH_NOALLOC_MAX_N)
+    return fail(BH_EINVAL, "n must be in [0, %d] for bh_forces_noalloc; got %lld (use bh_build_tree with a "
+                "workspace for larger sets)", BH_NOALLOC_MAX_N, (long long)n);
+  if (prec != BH_FP32 && prec != BH_FP64) return fail(BH_EINVAL, "prec must be BH_FP32 or BH_FP64");
+  int rc = check_theta_eps(theta, eps);
+  if (rc) return rc;
+  if (n == 0) return BH_OK;
+  const size_t el = prec == BH_FP64 ? 8 : 4;
+  if (!pos || !mass || !acc || !pot || !aligned(pos, el) || !aligned(mass, el) || !aligned(acc, el) ||
+      !aligned(pot, el))
+    return fail(BH_EINVAL, "pos/mass/acc/pot must be non-null device arrays aligned to %zu bytes", el);
+  const size_t need = layout(n, 1, prec, nullptr, nullptr, nullptr, nullptr);
+  if (need > (size_t)BH_NOALLOC_SCRATCH_BYTES)
+    return fail(BH_ENOSPC, "%zu bytes of scratch needed, %d held", need, BH_NOALLOC_SCRATCH_BYTES);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "reading the current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(BH_EINVAL, "device %d beyond the %d this entry serves", dev,
+                                                 kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  void* base = nullptr;
+  if ((rc = scratch_address(dev, &base)) != BH_OK) return rc;
+  // the same handle each call: default walk shape, fields reset (no events, no timing)
+  bh_tree& t = g_noalloc_tree[dev];
+  t = bh_tree{};
+  t.n = n;
+  t.n_seg = 1;
+  t.prec = prec;
+  t.pos = pos;
+  t.mass = mass;
+  layout(n, 1, prec, static_cast<char*>(base), &t.w, &t.rank, &t.queue);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // every array the build and the walk read is written by them first (counters
+  // and flags by fill kernels), so the previous call's contents do not matter
+  e = enqueue_build(&t, st);
+  if (e != hipSuccess) return hip_fail(e, "launching the tree build");
+  return run_walk(&t, theta, nullptr, eps, acc, pot, bh::kWalkForces, nullptr, nullptr, nullptr, 0, nullptr, st,
+                  false);
 }
 
 int bh_walk_stats(const bh_tree* t, double theta, const float* theta_group, double eps, void* acc, void* pot,
