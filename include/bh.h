@@ -141,6 +141,70 @@ BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double ep
 BH_API int bh_forces_noalloc(const void *pos, const void *mass, int64_t n, int prec, double theta, double eps,
                              void *acc, void *pot, void *stream);
 
+/* Order of the particle-cell terms of the tree's later walks (bh_forces,
+ * bh_forces_theta, bh_walk_stats, bh_graph_create): 1 (default) uses a cell's
+ * mass at its centre of mass, the monopole of Eq. (1); 2 adds the quadrupole
+ * correction, the second-order Taylor expansion of the cell's softened
+ * potential about its centre of mass (Sec. 4.1 allows any higher moment in the
+ * particle-cell term; Sec. 7 names higher multipoles as the next step):
+ *   acc += M d/rho^3 - 3 (B d)/rho^5 + (15/2 d.B.d/rho^7 - 3/2 T/rho^5) d
+ *   pot += -M/rho + (T/rho^3 - 3 d.B.d/rho^5) / 2
+ * with d = com - x_i, rho^2 = |d|^2 + eps^2, B the cell's second moments about
+ * its centre of mass (sum m y y^T) and T = tr B.  The opening test is the same,
+ * so the interaction lists are too.  The first walk of order 2 after a build
+ * computes every node's B (FP64) into the workspace.  Order-2 walks take one
+ * target per lane (bh_set_walk_config's targets_per_lane is ignored) and read
+ * nodes on the scalar route only.  Returns BH_EINVAL for other orders. */
+BH_API int bh_set_expansion_order(bh_tree *t, int order);
+
+/* One step of the time loop of Sec. 1 (forces, orbit integration, repeat):
+ * a kick-drift-kick leapfrog step of size dt with the tree forces of bh_forces
+ * (order 1 or 2, theta, eps as there):
+ *   v += dt/2 a;  x += dt v;  rebuild the tree;  a, pot = forces(x);  v += dt/2 a
+ * (each update in FP64, rounded once to the state's precision).
+ *   pos, vel, acc [n][3], mass, pot [n]: device, precision prec, updated in
+ *     place; acc must hold the forces of the current positions on entry (one
+ *     bh_forces call before the first step) and holds the new ones on exit.
+ *   ids [n] (int64, optional): carried along by the reorder.
+ *   reorder: 1 permutes pos, vel, mass, acc, pot and ids into the new tree's
+ *     Morton order after the step (Sec. 5: a code that rebuilds its tree every
+ *     step gets the localized order for free); the next build then reads
+ *     nearly sorted keys, and walking targets in input order walks them nearly
+ *     in Morton order.  0 leaves the caller's order.
+ *   workspace, ws_bytes: as for bh_build_tree (the step's tree lives there).
+ * Errors as for bh_build_tree and bh_forces; BH_EINVAL for a non-finite dt. */
+BH_API int bh_leapfrog_step(void *pos, void *vel, void *mass, void *acc, void *pot, int64_t *ids, int64_t n,
+                            int prec, double dt, double theta, double eps, int order, int reorder, void *workspace,
+                            int64_t ws_bytes, void *stream);
+
+/* Neighbour search by the general tree walk of Sec. 4.3 (Fig. 4): for every
+ * particle i, the particles j != i with |x_j - x_i|^2 < radius^2 (FP64 distance
+ * of the tree's coordinates), found by walking the tree and skipping every cell
+ * that cannot hold such a point.  Outputs in caller order:
+ *   count [n] (int32): number of neighbours;
+ *   hash [n]: ordered hash of the neighbours' caller indices j, in the walk's
+ *     depth-first (Morton) order, h = (h xor (j << 1)) * 1099511628211 from
+ *     14695981039346656037 (in a forest j is relative to the cluster's offset
+ *     and only the target's own cluster is searched);
+ *   lists [n][maxlen] (int64, optional): the first maxlen neighbours, in that
+ *     order (entries past the list are left as they were);
+ *   rho [n] (optional, tree precision): the SPH density, the per-neighbour work
+ *     of proc_particle here: rho_i = m_i W(0, h) + sum_j m_j W(r_ij, h) with
+ *     h = radius / 2 and W the M4 cubic spline of support 2h (Monaghan &
+ *     Lattanzio 1985), accumulated in FP64.
+ * Uses the tree's target order and XCD runs (bh_set_walk_config); overwrites
+ * the force walk's node copy (the next force walk rebuilds it). */
+BH_API int bh_neighbours(const bh_tree *t, double radius, int32_t *count, uint64_t *hash, int64_t *lists,
+                         int64_t maxlen, void *rho, void *stream);
+
+/* Copy out every node's second moments about its centre of mass (computing
+ * them first if no walk of order 2 has since the build): B [n_nodes][6] device
+ * doubles, (xx, xy, xz, yy, yz, zz) per node in depth-first preorder.  A leaf
+ * sums over its particles (one particle: 0); a cell adds its children's moments
+ * shifted to its own centre of mass (parallel-axis theorem), children in octant
+ * order.  Synchronises `stream`. */
+BH_API int bh_tree_moments2(const bh_tree *t, double *B, void *stream);
+
 /* The walk of bh_forces / bh_forces_theta (theta_group may be NULL) that also
  * records, per particle in caller order, counts [n][2] = (particle terms, cell
  * terms) and hash [n] = ordered-list hash: h = (h xor w) * 1099511628211 from

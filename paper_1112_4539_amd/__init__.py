@@ -14,7 +14,7 @@ import os
 
 import torch
 
-__all__ = ["Tree", "Forest", "Graph", "build_tree", "build_forest", "direct", "forces_noalloc", "workspace_bytes",
+__all__ = ["Tree", "Forest", "Graph", "build_tree", "build_forest", "direct", "forces_noalloc", "leapfrog_step", "workspace_bytes",
            "forest_workspace_bytes", "load", "THETA_MAX", "BHError", "FP32", "FP64", "WalkConfig"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +68,10 @@ def load():
         "bh_tree_export": ([P, P, P, P], i32),
         "bh_set_walk_config": ([P, i32, i32, i32, i32, i32, i32], i32),
         "bh_set_timing": ([P, i32], i32),
+        "bh_set_expansion_order": ([P, i32], i32),
+        "bh_tree_moments2": ([P, P, P], i32),
+        "bh_neighbours": ([P, d, P, P, P, i64, P, P], i32),
+        "bh_leapfrog_step": ([P, P, P, P, P, P, i64, i32, d, d, d, i32, i32, P, i64, P], i32),
         "bh_walk_time_ms": ([P, P], i32),
         "bh_tree_release": ([P], None),
         "bh_direct": ([P, P, i64, i32, P, i64, d, P, P, P], i32),
@@ -160,6 +164,7 @@ class Tree:
         self.device = self.pos.device
         self.offsets = None
         self.n_clusters = 1
+        self.order = 1
         if offsets is not None:
             if offsets.dtype != torch.int64 or offsets.device != self.device or offsets.dim() != 1 \
                     or offsets.shape[0] < 2:
@@ -245,6 +250,36 @@ class Tree:
     def graph(self, theta, eps, acc, pot):
         """Capture build + forces into acc/pot as one HIP graph (``bh_graph_create``)."""
         return Graph(self, theta, eps, acc, pot)
+
+    def neighbours(self, radius, maxlen=0, density=True):
+        """Neighbour search within ``radius`` (``bh_neighbours``): dict of count [n] int32, hash [n],
+        optional lists [n, maxlen] (caller indices, walk order) and the SPH density rho [n]."""
+        count = torch.empty((self.n,), dtype=torch.int32, device=self.device)
+        hsh = torch.empty((self.n,), dtype=torch.int64, device=self.device)
+        lists = torch.full((self.n, maxlen), -1, dtype=torch.int64, device=self.device) if maxlen > 0 else None
+        rho = torch.empty((self.n,), dtype=self.dtype, device=self.device) if density else None
+        _check(load().bh_neighbours(self._h, float(radius), _ptr(count), _ptr(hsh), _ptr(lists), int(maxlen),
+                                    _ptr(rho), _stream(self.device)))
+        out = dict(count=count, hash=hsh)
+        if lists is not None:
+            out["lists"] = lists
+        if rho is not None:
+            out["rho"] = rho
+        return out
+
+    def moments2(self):
+        """Second moments [n_nodes, 6] float64 (xx xy xz yy yz zz) of every node about its centre
+        of mass (``bh_tree_moments2``)."""
+        m = self.stats()["n_nodes"]
+        B = torch.empty((max(m, 1), 6), dtype=torch.float64, device=self.device)
+        _check(load().bh_tree_moments2(self._h, _ptr(B), _stream(self.device)))
+        return B[:m]
+
+    def set_order(self, order):
+        """Particle-cell terms of later walks: 1 monopole (Eq. (1)), 2 with the quadrupole
+        correction (``bh_set_expansion_order``)."""
+        _check(load().bh_set_expansion_order(self._h, int(order)))
+        self.order = int(order)
 
     def set_timing(self, enable=True):
         _check(load().bh_set_timing(self._h, 1 if enable else 0))
@@ -401,6 +436,27 @@ def build_tree(pos, mass, workspace=None):
 def build_forest(pos, mass, offsets, workspace=None):
     """One tree per cluster [offsets[k], offsets[k+1]) in one build (``bh_build_forest``)."""
     return Tree(pos, mass, workspace, offsets=offsets)
+
+
+def leapfrog_step(pos, vel, mass, acc, pot, dt, theta, eps, order=1, reorder=False, ids=None, workspace=None):
+    """One kick-drift-kick step of the time loop (``bh_leapfrog_step``), in place on the caller's
+    device state; ``acc`` must hold the forces of the current positions.  With ``reorder`` the
+    state (and ``ids``) is permuted into the new tree's Morton order."""
+    lib = load()
+    prec = _prec_of(pos.dtype)
+    n = int(pos.shape[0])
+    for t, shape in ((pos, (n, 3)), (vel, (n, 3)), (acc, (n, 3)), (mass, (n,)), (pot, (n,))):
+        if t.dtype != pos.dtype or tuple(t.shape) != shape or not t.is_contiguous() or t.device != pos.device:
+            raise ValueError("pos/vel/acc must be [n,3] and mass/pot [n], contiguous, one dtype and device")
+    if ids is not None and (ids.dtype != torch.int64 or ids.shape != (n,) or not ids.is_contiguous()):
+        raise ValueError("ids must be a contiguous int64 [n] tensor")
+    need = workspace_bytes(n, prec)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=pos.device)
+    _check(lib.bh_leapfrog_step(_ptr(pos), _ptr(vel), _ptr(mass), _ptr(acc), _ptr(pot), _ptr(ids), n, prec,
+                                float(dt), float(theta), float(eps), int(order), 1 if reorder else 0,
+                                _ptr(workspace), workspace.numel(), _stream(pos.device)))
+    return workspace
 
 
 NOALLOC_MAX_N = 65536

@@ -12,7 +12,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbh.so")
-SOURCES = ["bh_build.hip", "bh_walk.hip", "bh_direct.hip", "bh_learn.hip", "bh_api.hip"]
+SOURCES = ["bh_build.hip", "bh_walk.hip", "bh_walk_f32.hip", "bh_walk_f32s.hip", "bh_walk_f64.hip",
+           "bh_walk_f64s.hip", "bh_nbr.hip", "bh_step.hip", "bh_direct.hip", "bh_learn.hip", "bh_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950:xnack-", "-O3", "-std=c++17", "-fPIC",
@@ -23,7 +24,7 @@ FLAGS = [
 # The walk issues the next node record's load as soon as the opening test has
 # fixed the cursor, ahead of the terms; machine sinking would move that load
 # down into the next step, next to its use.
-EXTRA = {"bh_walk.hip": ["-mllvm", "-disable-machine-sink"]}
+EXTRA = {f"bh_walk{v}.hip": ["-mllvm", "-disable-machine-sink"] for v in ("", "_f32", "_f32s", "_f64", "_f64s")}
 BUILD_DIR = os.path.join(HERE, "_build")
 
 
@@ -46,7 +47,7 @@ def build(verbose=False, jobs=None):
     objs = [os.path.join(BUILD_DIR, src.replace(".hip", ".o")) for src in SOURCES]
     cmds = [[HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", "-o", obj, os.path.join(CSRC, src)]
             for src, obj in zip(SOURCES, objs)]
-    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for f in [ex.submit(_run, c, verbose) for c in cmds]:
             f.result()

@@ -30,6 +30,8 @@ struct bh_tree {
   int xcd_chunk = -1;  // -1: 1024 for FP32 trees (about the one-wave workgroups an XCD holds), 0 for FP64
   int target_order = 2;
   mutable bool horder_ready = false;  // w.horder holds the Hilbert order of the current build
+  int order = 1;                      // cell terms: 1 monopole, 2 with the quadrupole correction
+  mutable bool quad_ready = false;    // w.qrec holds the second moments of the current build
   int lds_share64 = 0;
   int persistent = 0;
   int targets_per_lane = 1;
@@ -124,6 +126,7 @@ size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_
   // cursor's last position before it tests the loop bound)
   t.wnodes = reinterpret_cast<bh::WalkNode*>(take(sizeof(bh::WalkNode) * (nodes + 1)));
   t.horder = reinterpret_cast<int32_t*>(take(4 * N));
+  t.qrec = reinterpret_cast<bh::QuadRec*>(take(sizeof(bh::QuadRec) * (nodes + 1)));
   int32_t* r = reinterpret_cast<int32_t*>(take(4 * N));
   if (w) *w = t;
   if (rank) *rank = r;
@@ -151,6 +154,7 @@ int sync_counts(const bh_tree* t, hipStream_t st, bh::Counts* c) {
 hipError_t enqueue_build(const bh_tree* t, hipStream_t st) {
   const int n = (int)t->n;
   t->horder_ready = false;
+  t->quad_ready = false;
   hipError_t e = t->prec == BH_FP64
                      ? bh::build_tree_f64(static_cast<const double*>(t->pos), static_cast<const double*>(t->mass), n,
                                           t->w, st)
@@ -197,8 +201,15 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
     if (e != hipSuccess) return hip_fail(e, "launching the Hilbert target order");
     t->horder_ready = true;
   }
+  if (t->order == 2 && !t->quad_ready) {
+    // (once per build, like the Hilbert order)
+    hipError_t e = bh::quad_moments(t->prec == BH_FP64, (int)t->n, t->w, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the second-moment passes");
+    t->quad_ready = true;
+  }
   bh::WalkArgs a{};
   a.nodes = t->w.nodes;
+  a.qrec = t->order == 2 ? t->w.qrec : nullptr;
   a.cnt = t->w.counts;
   a.bad_theta = &t->w.counts->bad_theta;
   a.wnodes = t->w.wnodes;
@@ -225,11 +236,11 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.lds_share64 = t->lds_share64;
   a.waves_per_block = t->waves_per_block;
   a.persistent = t->persistent;
-  a.targets_per_lane = t->targets_per_lane;
+  a.targets_per_lane = t->order == 2 ? 1 : t->targets_per_lane;  // (order 2: one target per lane)
   a.queue = t->queue;
   if (t->persistent) {
-    a.grid = bh::persistent_grid(t->prec == BH_FP64, mode, eps * eps > 0.0, theta_group != nullptr, t->waves_per_block,
-                                 t->targets_per_lane);
+    a.grid = bh::persistent_grid(t->prec == BH_FP64, t->order == 2 ? (mode | bh::kWalkQuad) : mode, eps * eps > 0.0,
+                                 theta_group != nullptr, t->waves_per_block, a.targets_per_lane);
     if (a.grid <= 0) return fail(BH_EHIP, "cannot size the persistent walk grid");
   }
   bh_tree* mt = const_cast<bh_tree*>(t);
@@ -238,7 +249,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
     hipError_t e = hipEventRecord(t->ev0, st);
     if (e != hipSuccess) return hip_fail(e, "recording the walk start event");
   }
-  hipError_t e = bh::launch_walk(t->prec == BH_FP64, mode, a, st);
+  hipError_t e = bh::launch_walk(t->prec == BH_FP64, t->order == 2 ? (mode | bh::kWalkQuad) : mode, a, st);
   if (e != hipSuccess) return hip_fail(e, "launching the tree walk");
   if (timing) {
     e = hipEventRecord(t->ev1, st);
@@ -438,6 +449,100 @@ int bh_tree_export(const bh_tree* t, void* nodes, int32_t* perm, void* stream) {
   return BH_OK;
 }
 
+int bh_leapfrog_step(void* pos, void* vel, void* mass, void* acc, void* pot, int64_t* ids, int64_t n, int prec,
+                     double dt, double theta, double eps, int order, int reorder, void* workspace, int64_t ws_bytes,
+                     void* stream) {
+  if (n < 0 || n > kMaxN) return fail(BH_EINVAL, "n must be in [0, 2^30 - 1]; got %lld", (long long)n);
+  if (prec != BH_FP32 && prec != BH_FP64) return fail(BH_EINVAL, "prec must be BH_FP32 or BH_FP64");
+  if (!std::isfinite(dt)) return fail(BH_EINVAL, "dt must be finite");
+  if (order != 1 && order != 2) return fail(BH_EINVAL, "order must be 1 or 2");
+  if (reorder != 0 && reorder != 1) return fail(BH_EINVAL, "reorder must be 0 or 1");
+  int rc = check_theta_eps(theta, eps);
+  if (rc) return rc;
+  if (n == 0) return BH_OK;
+  const size_t el = prec == BH_FP64 ? 8 : 4;
+  if (!pos || !vel || !mass || !acc || !pot || !aligned(pos, el) || !aligned(vel, el) || !aligned(mass, el) ||
+      !aligned(acc, el) || !aligned(pot, el) || (ids && !aligned(ids, 8)))
+    return fail(BH_EINVAL, "pos/vel/mass/acc/pot must be non-null device arrays aligned to %zu bytes", el);
+  const int64_t need = bh_workspace_bytes(n, prec);
+  if (!workspace || ws_bytes < need)
+    return fail(BH_ENOSPC, "workspace of %lld bytes needed, %lld given", (long long)need, (long long)ws_bytes);
+  if (!aligned(workspace, kAlign)) return fail(BH_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool f64 = prec == BH_FP64;
+  bh_tree t;
+  t.n = n;
+  t.n_seg = 1;
+  t.prec = prec;
+  t.pos = pos;
+  t.mass = mass;
+  t.order = order;
+  layout(n, 1, prec, static_cast<char*>(workspace), &t.w, &t.rank, &t.queue);
+  // kick and drift with the forces of the current positions, rebuild, new forces, kick
+  hipError_t e = bh::launch_kick_drift(f64, pos, vel, acc, (int)n, dt, st);
+  if (e != hipSuccess) return hip_fail(e, "launching the kick-drift pass");
+  e = enqueue_build(&t, st);
+  if (e != hipSuccess) return hip_fail(e, "launching the tree build");
+  rc = run_walk(&t, theta, nullptr, eps, acc, pot, bh::kWalkForces, nullptr, nullptr, nullptr, 0, nullptr, st, false);
+  if (rc) return rc;
+  e = bh::launch_kick(f64, vel, acc, (int)n, dt, st);
+  if (e != hipSuccess) return hip_fail(e, "launching the kick pass");
+  if (reorder) {
+    // (the walk copy of the nodes is free once the walk is done: 128 bytes per particle)
+    e = bh::launch_reorder(f64, t.w.idx_a, (int)n, pos, vel, mass, acc, pot, ids, t.w.wnodes, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the Morton reorder");
+  }
+  return BH_OK;
+}
+
+int bh_neighbours(const bh_tree* t, double radius, int32_t* count, uint64_t* hash, int64_t* lists, int64_t maxlen,
+                  void* rho, void* stream) {
+  if (!t) return fail(BH_EINVAL, "null tree");
+  if (!(radius > 0.0) || !std::isfinite(radius)) return fail(BH_EINVAL, "radius must be finite and > 0; got %g", radius);
+  if (t->n == 0) return BH_OK;
+  if (!count || !hash || !aligned(count, 4) || !aligned(hash, 8))
+    return fail(BH_EINVAL, "count/hash must be non-null aligned device arrays");
+  if (lists && (maxlen <= 0 || !aligned(lists, 8)))
+    return fail(BH_EINVAL, "lists must be an aligned device array with maxlen > 0");
+  const size_t el = t->prec == BH_FP64 ? 8 : 4;
+  if (rho && !aligned(rho, el)) return fail(BH_EINVAL, "rho must be aligned to %zu bytes", el);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (t->target_order == 2 && !t->horder_ready) {
+    hipError_t e = bh::hilbert_order(t->prec == BH_FP64, (int)t->n, t->w, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the Hilbert target order");
+    t->horder_ready = true;
+  }
+  const int32_t* order = t->target_order == 1 ? t->rank : t->target_order == 2 ? t->w.horder : nullptr;
+  const int chunk = t->xcd_chunk >= 0 ? t->xcd_chunk : (t->prec == BH_FP64 ? 0 : 1024);
+  hipError_t e = bh::launch_neighbours(t->prec == BH_FP64, t->w.nodes, t->w.counts, t->w.wnodes, t->w.ps, t->w.idx_a,
+                                       order, t->n_seg > 1 ? t->w.scid : nullptr, t->w.croot, t->w.seg_off,
+                                       (int)t->n_seg, (int)t->n, radius, count, hash, lists, lists ? maxlen : 0, rho,
+                                       chunk, st);
+  if (e != hipSuccess) return hip_fail(e, "launching the neighbour walk");
+  return BH_OK;
+}
+
+int bh_tree_moments2(const bh_tree* t, double* B, void* stream) {
+  if (!t) return fail(BH_EINVAL, "null tree");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bh::Counts c{};
+  int rc = sync_counts(t, st, &c);
+  if (rc) return rc;
+  if (t->n == 0) return BH_OK;
+  if (!B || !aligned(B, 8)) return fail(BH_EINVAL, "B must be a non-null device array of doubles");
+  if (!t->quad_ready) {
+    hipError_t e = bh::quad_moments(t->prec == BH_FP64, (int)t->n, t->w, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the second-moment passes");
+    t->quad_ready = true;
+  }
+  // (the records hold B in their first 48 bytes)
+  hipError_t e = hipMemcpy2DAsync(B, 6 * sizeof(double), t->w.qrec, sizeof(bh::QuadRec), 6 * sizeof(double),
+                                  (size_t)c.n_nodes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "copying the second moments");
+  return BH_OK;
+}
+
 int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int target_order, int lds_share,
                        int persistent, int targets_per_lane) {
   if (!t) return fail(BH_EINVAL, "null tree");
@@ -454,6 +559,13 @@ int bh_set_walk_config(bh_tree* t, int waves_per_block, int xcd_chunk, int targe
   t->waves_per_block = waves_per_block;
   t->xcd_chunk = xcd_chunk;
   t->target_order = target_order;
+  return BH_OK;
+}
+
+int bh_set_expansion_order(bh_tree* t, int order) {
+  if (!t) return fail(BH_EINVAL, "null tree");
+  if (order != 1 && order != 2) return fail(BH_EINVAL, "order must be 1 (monopole) or 2 (quadrupole)");
+  t->order = order;
   return BH_OK;
 }
 
@@ -535,8 +647,9 @@ int bh_graph_create(bh_tree* t, double theta, double eps, void* acc, void* pot, 
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     // nothing captured has run: an eager walk before the first replay must
-    // form the Hilbert order itself
+    // form the Hilbert order and the second moments itself
     t->horder_ready = false;
+    t->quad_ready = false;
     if (eb != hipSuccess) e = eb;
     if (e == hipSuccess && wrc != BH_OK) {
       if (graph) (void)hipGraphDestroy(graph);

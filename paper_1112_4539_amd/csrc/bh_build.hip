@@ -1034,6 +1034,92 @@ hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st) {
   return f64 ? hilbert_impl<double4>(n, w, st) : hilbert_impl<float4>(n, w, st);
 }
 
+// ---------------------------------------------------------------- second moments
+// Quadrupole cell terms (walks of order 2) need each node's second moments
+// about its centre of mass.  A leaf sums over its particles (one particle: 0);
+// a cell takes its children's moments shifted to its own centre of mass by the
+// parallel-axis theorem, B = sum_c (B_c + M_c d_c d_c^T) with d_c = com_c -
+// com, children in octant order, one pass per level, deepest first.
+__device__ __forceinline__ void put_quad(QuadRec* __restrict__ qr, int p, const double b[6]) {
+  QuadRec q;
+  q.bxx = b[0];
+  q.bxy = b[1];
+  q.bxz = b[2];
+  q.byy = b[3];
+  q.byz = b[4];
+  q.bzz = b[5];
+  q.T = b[0] + b[3] + b[5];
+  q.pad = 0.0;
+  qr[p] = q;
+}
+
+template <typename T4>
+__global__ __launch_bounds__(256) void k_quad_leaf(const Counts* __restrict__ cnt, const int32_t* __restrict__ nstart,
+                                                   const int32_t* __restrict__ nexcl, const int32_t* __restrict__ ustart,
+                                                   const T4* __restrict__ ps, const Node* __restrict__ nodes,
+                                                   QuadRec* __restrict__ qr, int nmax) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nmax || x >= cnt->n_unique) return;
+  const int pre = x + nexcl[x] + nstart[x];
+  const int first = ustart[x], count = ustart[x + 1] - first;
+  double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (count > 1) {
+    const Node nd = nodes[pre];
+    for (int k = first; k < first + count; ++k) {
+      const T4 q = ps[k];
+      const double m = (double)q.w;
+      const double y0 = (double)q.x - nd.cx, y1 = (double)q.y - nd.cy, y2 = (double)q.z - nd.cz;
+      b[0] += m * y0 * y0;
+      b[1] += m * y0 * y1;
+      b[2] += m * y0 * y2;
+      b[3] += m * y1 * y1;
+      b[4] += m * y1 * y2;
+      b[5] += m * y2 * y2;
+    }
+  }
+  put_quad(qr, pre, b);
+}
+
+__global__ __launch_bounds__(256) void k_quad_level(const Counts* __restrict__ cnt, const int32_t* __restrict__ ilevel,
+                                                    const int32_t* __restrict__ ipre, const Node* __restrict__ nodes,
+                                                    const int32_t* __restrict__ nx, QuadRec* __restrict__ qr, int level,
+                                                    int nmax) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nmax || v >= cnt->n_internal || ilevel[v] != level) return;
+  const int p = ipre[v];
+  const int end = min(nx[p], cnt->n_nodes);
+  const Node np = nodes[p];
+  double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = p + 1;
+  for (int k = 0; k < 8 && c < end; ++k, c = max(nx[c], c + 1)) {
+    const Node nc = nodes[c];
+    const QuadRec q = qr[c];
+    const double d0 = nc.cx - np.cx, d1 = nc.cy - np.cy, d2 = nc.cz - np.cz;
+    const double m0 = nc.M * d0, m1 = nc.M * d1, m2 = nc.M * d2;
+    b[0] += q.bxx + m0 * d0;
+    b[1] += q.bxy + m0 * d1;
+    b[2] += q.bxz + m0 * d2;
+    b[3] += q.byy + m1 * d1;
+    b[4] += q.byz + m1 * d2;
+    b[5] += q.bzz + m2 * d2;
+  }
+  put_quad(qr, p, b);
+}
+
+template <typename T4>
+static hipError_t quad_impl(int n, const BuildWs& w, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_quad_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.nstart, w.nexcl, w.ustart,
+                                                reinterpret_cast<const T4*>(w.ps), w.nodes, w.qrec, n);
+  for (int level = kLevels - 1; level >= 0; --level)
+    k_quad_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.ilevel, w.ipre, w.nodes, w.nx, w.qrec, level, n);
+  return hipGetLastError();
+}
+
+hipError_t quad_moments(bool f64, int n, const BuildWs& w, hipStream_t st) {
+  return f64 ? quad_impl<double4>(n, w, st) : quad_impl<float4>(n, w, st);
+}
+
 hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st) {
   return build_impl<float, float4>(pos, mass, n, w, st);
 }

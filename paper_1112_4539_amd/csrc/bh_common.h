@@ -73,6 +73,17 @@ struct alignas(64) ThetaNode {
 };
 static_assert(sizeof(ThetaNode) == 64, "ThetaNode must be 64 bytes");
 
+// Second moments of a node for walks of order 2 (quadrupole cell terms):
+// B_ab = sum over the node's particles of m (x_a - com_a)(x_b - com_b), FP64,
+// and T = Bxx + Byy + Bzz.  A one-particle leaf has B = 0.  Read by the walk
+// beside the node's walk record, with the same index.
+struct alignas(64) QuadRec {
+  double bxx, bxy, bxz, byy, byz, bzz;
+  double T;
+  double pad;
+};
+static_assert(sizeof(QuadRec) == 64, "QuadRec must be 64 bytes");
+
 // Root cube and Morton quantisation, computed on the device by the bbox pass.
 struct Cube {
   double lo[3];   // coordinate-wise minimum of the particles

@@ -55,6 +55,7 @@ struct BuildWs {
   int32_t* nx;              // [2n] next(c) of every node, for the moment passes
   WalkNode* wnodes;         // [2n] walk copy of the nodes for the last uniform theta
   int32_t* horder;          // [n] Morton positions in the Hilbert walk order (filled on demand)
+  QuadRec* qrec;            // [2n + 1] second moments of every node (walks of order 2; filled on demand)
 };
 
 hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total, hipStream_t st);
@@ -66,6 +67,9 @@ hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // Uses the sort buffers of the build, so it runs after it; w.key_a, w.key_b
 // and w.idx_b are overwritten.
 hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st);
+// Second moments of every node about its centre of mass (w.qrec), for walks of
+// order 2; runs after the build (reads its nodes and topology arrays).
+hipError_t quad_moments(bool f64, int n, const BuildWs& w, hipStream_t st);
 
 // Tree walk launch.  Targets are processed in groups of 64 (one wavefront);
 // group g holds the targets at positions [64g, 64g+64) of `order` (Morton
@@ -87,6 +91,7 @@ struct WalkArgs {
   const WalkNode* wnodes;      // uniform theta: walk copy of the nodes (S and M32 precomputed)
   const ThetaNode* tnodes;     // per-group theta, FP32: walk copy with l and s (same memory as wnodes)
   const float* theta_group;    // theta per 64-particle Morton group, may be null
+  const QuadRec* qrec;         // order 2: second moments of every node (cell terms with the quadrupole)
   void* acc;                   // [n][3] caller order
   void* pot;                   // [n] caller order
   int32_t* counts;             // stats: [n][2] = (particle terms, cell terms), caller order
@@ -104,6 +109,8 @@ struct WalkArgs {
 };
 
 enum WalkMode { kWalkForces = 0, kWalkStats = 1, kWalkDump = 2 };
+// Added to a mode: cell terms of order 2 (monopole plus quadrupole correction).
+constexpr int kWalkQuad = 4;
 
 hipError_t launch_walk(bool f64, int mode, const WalkArgs& a, hipStream_t st);
 
@@ -142,6 +149,21 @@ hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, floa
 
 // Walk copy of the nodes for per-group theta (FP32 walks).
 hipError_t launch_theta_copy(const Node* nodes, const Counts* counts, int cap, ThetaNode* tnodes, hipStream_t st);
+
+// Neighbour search (the general tree walk of Fig. 4): per target the particles
+// within `radius`, their ordered hash, optional lists and the SPH density.
+// `copy` receives the walk copy (2n + 1 records; the force walk's buffer).
+hipError_t launch_neighbours(bool f64, const Node* nodes, const Counts* counts, WalkNode* copy, const void* ps,
+                             const int32_t* perm, const int32_t* order, const int32_t* scid, const int32_t* croot,
+                             const int64_t* seg_off, int n_seg, int n, double radius, int32_t* count,
+                             uint64_t* hash, int64_t* lists, int64_t maxlen, void* rho, int xcd_chunk,
+                             hipStream_t st);
+
+// Time loop (bh_step.hip): leapfrog updates and the Morton reorder of the state.
+hipError_t launch_kick_drift(bool f64, void* pos, void* vel, const void* acc, int n, double dt, hipStream_t st);
+hipError_t launch_kick(bool f64, void* vel, const void* acc, int n, double dt, hipStream_t st);
+hipError_t launch_reorder(bool f64, const int32_t* perm, int n, void* pos, void* vel, void* mass, void* acc,
+                          void* pot, int64_t* ids, void* tmp, hipStream_t st);
 
 // Direct sum of Eq. (1) for a list of targets (caller indices).
 hipError_t launch_direct(bool f64, const void* pos, const void* mass, int n, const int64_t* targets, int nt,
