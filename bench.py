@@ -50,27 +50,43 @@ def measured_traffic(workload, theta):
     return rec["traffic_bytes"]
 
 
-def cpu_baseline(pos32, mass32, theta, eps, seed, n_sample):
-    """The FP64 CPU oracle on this host: full tree build + walk of a target sample, scaled."""
+def cpu_baseline(pos32, mass32, theta, eps, seed, n_sample, n_sample_1t):
+    """The FP64 CPU oracle on this host: full tree build + walk of a target sample, scaled to all
+    targets; on all the threads OpenMP gives it, and on one thread (walk sample n_sample_1t; the
+    tree build is serial code in both)."""
     import oracle
+    from paper_1112_4539_amd import inputs
     p64 = pos32.astype(np.float64)
     m64 = mass32.astype(np.float64)
+    n = len(p64)
     t0 = time.perf_counter()
     T = oracle.Tree(p64, m64)
     t1 = time.perf_counter()
-    from paper_1112_4539_amd import inputs
-    tg = inputs.sample_targets(len(p64), n_sample, seed + 7)
-    w = T.walk(theta, eps, targets=tg)
-    t2 = time.perf_counter()
-    n = len(p64)
-    inter = float(np.sum(w["n_pp"] + w["n_pc"]))
-    scale = n / len(tg)
-    t_total = (t1 - t0) + (t2 - t1) * scale
-    return dict(value=inter * scale / t_total, unit="interactions/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"FP64 oracle: tree build of all {n} particles ({t1 - t0:.2f} s) + walk of {len(tg)} "
-                       f"sampled targets ({t2 - t1:.2f} s), walk time scaled by {scale:.1f} to all targets",
-                build_s=t1 - t0, walk_sample_s=t2 - t1)
+    cores = oracle.num_threads()
+
+    def walk(count, salt):
+        tg = inputs.sample_targets(n, count, seed + salt)
+        s0 = time.perf_counter()
+        w = T.walk(theta, eps, targets=tg)
+        s1 = time.perf_counter()
+        inter = float(np.sum(w["n_pp"] + w["n_pc"]))
+        scale = n / len(tg)
+        t_total = (t1 - t0) + (s1 - s0) * scale
+        return inter * scale / t_total, len(tg), s1 - s0, scale
+
+    v, k, ws, scale = walk(n_sample, 7)
+    oracle.set_num_threads(1)
+    try:
+        v1, k1, ws1, scale1 = walk(n_sample_1t, 8)
+    finally:
+        oracle.set_num_threads(cores)
+    return dict(value=v, unit="interactions/s", cores=cores, kind="oracle",
+                sample=f"FP64 oracle: tree build of all {n} particles ({t1 - t0:.2f} s, serial) + walk of {k} "
+                       f"sampled targets ({ws:.2f} s on {cores} threads), walk time scaled by {scale:.1f} to all "
+                       f"targets",
+                one_thread={"value": v1, "unit": "interactions/s", "cores": 1,
+                            "sample": f"same build + walk of {k1} sampled targets on 1 thread ({ws1:.2f} s), "
+                                      f"scaled by {scale1:.1f}"})
 
 
 def forest_bench(args, bh, inputs):
@@ -336,6 +352,25 @@ def cube_bench(args, bh, inputs):
     print(json.dumps(line), flush=True)
 
 
+def walk_only(args, bh, inputs):
+    """One build and WALK_ONLY force walks of a named workload, nothing else: the command that
+    the rocprofv3 counter and trace summaries are taken from (target order, expansion order and
+    theta as given).  Prints the interactions of one walk."""
+    pos, mass, spec = inputs.make(args.workload)
+    dev = torch.device("cuda:0")
+    gpos = torch.tensor(pos.astype(np.float32), device=dev)
+    gmass = torch.tensor(mass.astype(np.float32), device=dev)
+    T = bh.Tree(gpos, gmass)
+    T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share, args.persistent,
+                      args.targets_per_lane)
+    T.set_order(args.order)
+    for _ in range(args.walk_only):
+        T.forces(args.theta, spec["eps"])
+    torch.cuda.synchronize()
+    log(f"[bench] walk-only: {args.workload} n={len(pos)} theta={args.theta} target_order={args.target_order} "
+        f"order={args.order}: {args.walk_only} walks")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,12 +382,16 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=262144)
+    ap.add_argument("--cpu-sample-1t", type=int, default=16384, help="walk sample of the one-thread CPU figure")
     ap.add_argument("--waves-per-block", type=int, default=1)
     ap.add_argument("--xcd-chunk", type=int, default=-1)
     ap.add_argument("--target-order", type=int, default=2)
     ap.add_argument("--lds-share", type=int, default=0)
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--targets-per-lane", type=int, default=1)
+    ap.add_argument("--order", type=int, default=1, help="cell terms: 1 monopole, 2 with the quadrupole")
+    ap.add_argument("--walk-only", type=int, default=0, metavar="K",
+                    help="only build once and run K force walks of --workload (for profiler runs)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -367,6 +406,8 @@ def main():
 
     if args.workload == "clusters512":
         return forest_bench(args, bh, inputs)
+    if args.walk_only:
+        return walk_only(args, bh, inputs)
     if args.workload == "plummer1m":
         return sweep_bench(args, bh, inputs)
     if args.workload == "learned":
@@ -500,8 +541,8 @@ def main():
     }
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
-        cb = cpu_baseline(pos32, mass32, args.theta, eps, spec["seed"], args.cpu_sample)
-        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        cb = cpu_baseline(pos32, mass32, args.theta, eps, spec["seed"], args.cpu_sample, args.cpu_sample_1t)
+        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "one_thread")}
     print(json.dumps(line), flush=True)
 
 

@@ -15,6 +15,8 @@ this module only loads it and marshals numpy arrays.  Definitions followed:
   ``order=2`` adds the quadrupole cell term (Sec. 4.1, Sec. 7: higher moments).
 * ``Tree.neighbours`` -- Sec. 4.3, Fig. 4: the general tree walk as a neighbour
   search with the SPH density as its per-neighbour work.
+* ``leapfrog``    -- Sec. 1: the time loop (forces, orbit integration, repeat), as the
+  kick-drift-kick leapfrog on the direct-sum forces.
 * ``rms_rel_err`` / ``mean_rel_err`` -- Sec. 5, Eq. (4) and its RMS form.
 """
 from __future__ import annotations
@@ -77,6 +79,10 @@ def _load():
     lib.orc_neighbours.restype = ctypes.c_int
     lib.orc_neighbours_brute.argtypes = [P, P, i64, P, i64, d, P, P]
     lib.orc_neighbours_brute.restype = ctypes.c_int
+    lib.orc_leapfrog.argtypes = [P, P, P, i64, d, d, i64, P, P]
+    lib.orc_leapfrog.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -96,6 +102,11 @@ def _as_pos(pos):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    _load().orc_set_num_threads(int(n))
 
 
 def direct(pos, mass, eps, targets=None):
@@ -201,6 +212,26 @@ class Tree:
         if lists is not None:
             out["lists"] = lists
         return out
+
+
+def leapfrog(pos, vel, mass, eps, dt, steps, acc=None):
+    """Kick-drift-kick leapfrog on the direct-sum forces (Sec. 1: force, integrate, repeat).
+
+    Returns (pos, vel, acc, pot) after ``steps`` steps of size ``dt`` (copies; the inputs are not
+    changed).  ``acc`` is a(x) of the initial positions (computed if None)."""
+    lib = _load()
+    pos = np.array(_as_pos(pos), dtype=np.float64)
+    vel = np.array(_as_pos(vel), dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = pos.shape[0]
+    if acc is None:
+        acc, pot, _ = direct(pos, mass, eps)
+    acc = np.array(acc, dtype=np.float64)
+    pot = np.zeros(n)
+    if lib.orc_leapfrog(_ptr(pos), _ptr(vel), _ptr(mass), n, float(eps), float(dt), int(steps), _ptr(acc),
+                        _ptr(pot)) != 0:
+        raise ValueError("orc_leapfrog rejected its arguments")
+    return pos, vel, acc, pot
 
 
 def sph_kernel(r, h):

@@ -45,6 +45,9 @@
  *                           outside the search ball, proc_cell does nothing.  The
  *                           per-neighbour work here is the SPH density sum with
  *                           the M4 cubic spline kernel (Monaghan & Lattanzio 1985).
+ *   time loop ............. Sec. 1: forces, then orbit integration, repeated.  The
+ *                           integrator is the kick-drift-kick leapfrog on the
+ *                           direct-sum forces.
  *   quadrupole cell term .. Sec. 4.1 allows any higher moment in the particle-cell
  *                           term and Sec. 7 names higher multipoles as the next
  *                           step.  Order 2 here is the second-order Taylor
@@ -628,6 +631,38 @@ int orc_neighbours_brute(const double *pos, const double *mass, int64_t n, const
     if (rho) rho[k] = rh;
   }
   return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Time loop (Sec. 1): forces, orbit integration, repeat.                     */
+/* ------------------------------------------------------------------------- */
+
+/* `steps` kick-drift-kick leapfrog steps of size dt on the direct-sum forces
+ * of Eq. (1): v += dt/2 a(x); x += dt v; v += dt/2 a(x).  pos, vel [n][3] are
+ * advanced in place; acc [n][3] and pot [n] end as the forces at the final
+ * positions (acc must hold a(x) of the initial positions on entry). */
+int orc_leapfrog(double *pos, double *vel, const double *mass, int64_t n, double eps, double dt, int64_t steps,
+                 double *acc, double *pot) {
+  if (n < 0 || steps < 0 || eps < 0) return -1;
+  for (int64_t s = 0; s < steps; ++s) {
+    for (int64_t k = 0; k < 3 * n; ++k) {
+      vel[k] += 0.5 * dt * acc[k];
+      pos[k] += dt * vel[k];
+    }
+    if (orc_direct(pos, mass, n, NULL, n, eps, acc, pot, NULL) != 0) return -1;
+    for (int64_t k = 0; k < 3 * n; ++k) vel[k] += 0.5 * dt * acc[k];
+  }
+  return 0;
+}
+
+/* Threads the parallel loops use from now on (n >= 1); for timing the oracle on
+ * one core beside all of them. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 int orc_num_threads(void) {
