@@ -197,6 +197,14 @@ BH_API int bh_leapfrog_step(void *pos, void *vel, void *mass, void *acc, void *p
 BH_API int bh_neighbours(const bh_tree *t, double radius, int32_t *count, uint64_t *hash, int64_t *lists,
                          int64_t maxlen, void *rho, void *stream);
 
+/* The order in which the walk takes its targets, as caller indices: order [n]
+ * (device int32), order[64g .. 64g+63] being the targets of wavefront g.  With
+ * target_order 2 (the default; bh_set_walk_config) it is the order of the
+ * Hilbert index of each particle's cell ten levels below the root cube (fewer
+ * in a forest, whose clusters come one after the other), ties in Morton order;
+ * 0 gives the Morton order, 1 the caller's order.  Synchronises `stream`. */
+BH_API int bh_walk_order(const bh_tree *t, int32_t *order, void *stream);
+
 /* Copy out every node's second moments about its centre of mass (computing
  * them first if no walk of order 2 has since the build): B [n_nodes][6] device
  * doubles, (xx, xy, xz, yy, yz, zz) per node in depth-first preorder.  A leaf

@@ -71,6 +71,7 @@ def load():
         "bh_set_expansion_order": ([P, i32], i32),
         "bh_tree_moments2": ([P, P, P], i32),
         "bh_neighbours": ([P, d, P, P, P, i64, P, P], i32),
+        "bh_walk_order": ([P, P, P], i32),
         "bh_leapfrog_step": ([P, P, P, P, P, P, i64, i32, d, d, d, i32, i32, P, i64, P], i32),
         "bh_walk_time_ms": ([P, P], i32),
         "bh_tree_release": ([P], None),
@@ -266,6 +267,12 @@ class Tree:
         if rho is not None:
             out["rho"] = rho
         return out
+
+    def walk_order(self):
+        """Caller indices of the targets in the order the walk takes them (``bh_walk_order``)."""
+        out = torch.empty((max(self.n, 1),), dtype=torch.int32, device=self.device)
+        _check(load().bh_walk_order(self._h, _ptr(out), _stream(self.device)))
+        return out[: self.n]
 
     def moments2(self):
         """Second moments [n_nodes, 6] float64 (xx xy xz yy yz zz) of every node about its centre

@@ -522,6 +522,23 @@ int bh_neighbours(const bh_tree* t, double radius, int32_t* count, uint64_t* has
   return BH_OK;
 }
 
+int bh_walk_order(const bh_tree* t, int32_t* order, void* stream) {
+  if (!t) return fail(BH_EINVAL, "null tree");
+  if (t->n == 0) return BH_OK;
+  if (!order || !aligned(order, 4)) return fail(BH_EINVAL, "order must be a non-null device array of int32");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (t->target_order == 2 && !t->horder_ready) {
+    hipError_t e = bh::hilbert_order(t->prec == BH_FP64, (int)t->n, t->w, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the Hilbert target order");
+    t->horder_ready = true;
+  }
+  const int32_t* pos_order = t->target_order == 1 ? t->rank : t->target_order == 2 ? t->w.horder : nullptr;
+  hipError_t e = bh::launch_walk_order(pos_order, t->w.idx_a, (int)t->n, order, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "writing the walk order");
+  return BH_OK;
+}
+
 int bh_tree_moments2(const bh_tree* t, double* B, void* stream) {
   if (!t) return fail(BH_EINVAL, "null tree");
   hipStream_t st = static_cast<hipStream_t>(stream);

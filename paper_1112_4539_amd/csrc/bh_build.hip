@@ -1030,6 +1030,20 @@ static hipError_t hilbert_impl(int n, const BuildWs& w, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The walk order of the targets as caller indices: out[k] = perm[order[k]]
+// (order: Morton positions in walk order; null = Morton order itself).
+__global__ __launch_bounds__(256) void k_walk_order(const int32_t* __restrict__ order, const int32_t* __restrict__ perm,
+                                                    int n, int32_t* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = perm[order ? order[k] : k];
+}
+
+hipError_t launch_walk_order(const int32_t* order, const int32_t* perm, int n, int32_t* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_walk_order<<<nblk(n, 256), 256, 0, st>>>(order, perm, n, out);
+  return hipGetLastError();
+}
+
 hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st) {
   return f64 ? hilbert_impl<double4>(n, w, st) : hilbert_impl<float4>(n, w, st);
 }
@@ -1048,8 +1062,9 @@ __device__ __forceinline__ void put_quad(QuadRec* __restrict__ qr, int p, const 
   q.byy = b[3];
   q.byz = b[4];
   q.bzz = b[5];
-  q.T = b[0] + b[3] + b[5];
-  q.pad = 0.0;
+  const double T = b[0] + b[3] + b[5];
+  q.t05 = 0.5 * T;
+  q.nt15 = -1.5 * T;
   qr[p] = q;
 }
 

@@ -75,12 +75,13 @@ static_assert(sizeof(ThetaNode) == 64, "ThetaNode must be 64 bytes");
 
 // Second moments of a node for walks of order 2 (quadrupole cell terms):
 // B_ab = sum over the node's particles of m (x_a - com_a)(x_b - com_b), FP64,
-// and T = Bxx + Byy + Bzz.  A one-particle leaf has B = 0.  Read by the walk
-// beside the node's walk record, with the same index.
+// with T = Bxx + Byy + Bzz kept as T/2 (exact) and -3T/2, the two forms the
+// term uses.  A one-particle leaf has B = 0.  Read by the walk beside the
+// node's walk record, with the same index.
 struct alignas(64) QuadRec {
   double bxx, bxy, bxz, byy, byz, bzz;
-  double T;
-  double pad;
+  double t05;    // T / 2
+  double nt15;   // -3T / 2
 };
 static_assert(sizeof(QuadRec) == 64, "QuadRec must be 64 bytes");
 

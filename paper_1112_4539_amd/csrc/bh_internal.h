@@ -67,6 +67,9 @@ hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // Uses the sort buffers of the build, so it runs after it; w.key_a, w.key_b
 // and w.idx_b are overwritten.
 hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st);
+// The targets' walk order as caller indices (order: Morton positions, null =
+// Morton order).
+hipError_t launch_walk_order(const int32_t* order, const int32_t* perm, int n, int32_t* out, hipStream_t st);
 // Second moments of every node about its centre of mass (w.qrec), for walks of
 // order 2; runs after the build (reads its nodes and topology arrays).
 hipError_t quad_moments(bool f64, int n, const BuildWs& w, hipStream_t st);

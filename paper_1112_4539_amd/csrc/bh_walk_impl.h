@@ -68,10 +68,10 @@ struct MixedTerm {
 // part of the Taylor expansion of the cell's softened potential about its
 // centre of mass.  With d = com - x_i (FP64), rho^-1 = ri, second moments B
 // and T = tr B:
-//   acc += (7.5 dBd rho^-7 - 1.5 T rho^-5) d - 3 rho^-5 B d
-//   pot += (T rho^-3 - 3 dBd rho^-5) / 2
+//   acc += rho^-5 (7.5 dBd rho^-2 - 1.5 T) d - 3 rho^-5 B d
+//   pot += rho^-3 (T/2 - 1.5 dBd rho^-2)
 // evaluated in FP64 (it is a small correction to the monopole; FP64 costs the
-// FP32 rate here and needs no conversions of d).
+// FP32 rate here and needs no conversions of d), in fused form.
 struct QuadPart {
   double c;            // coefficient of d
   double k;            // coefficient of B d (-3 rho^-5)
@@ -80,19 +80,19 @@ struct QuadPart {
 };
 __device__ __forceinline__ QuadPart quad_part(double dx, double dy, double dz, double ri, const QuadRec& q) {
   QuadPart r;
-  r.bx = q.bxx * dx + q.bxy * dy + q.bxz * dz;
-  r.by = q.bxy * dx + q.byy * dy + q.byz * dz;
-  r.bz = q.bxz * dx + q.byz * dy + q.bzz * dz;
-  const double dbd = dx * r.bx + dy * r.by + dz * r.bz;
+  r.bx = fma(q.bxz, dz, fma(q.bxy, dy, q.bxx * dx));
+  r.by = fma(q.byz, dz, fma(q.byy, dy, q.bxy * dx));
+  r.bz = fma(q.bzz, dz, fma(q.byz, dy, q.bxz * dx));
+  const double dbd = fma(dz, r.bz, fma(dy, r.by, dx * r.bx));
   const double ri2 = ri * ri;
   const double ri3 = ri * ri2;
   const double ri5 = ri3 * ri2;
-  const double ri7 = ri5 * ri2;
-  r.c = 7.5 * dbd * ri7 - 1.5 * q.T * ri5;
+  r.c = ri5 * fma(7.5 * dbd, ri2, q.nt15);
   r.k = -3.0 * ri5;
-  r.pq = 0.5 * (q.T * ri3 - 3.0 * dbd * ri5);
+  r.pq = ri3 * fma(-1.5 * dbd, ri2, q.t05);
   return r;
 }
+
 struct AccMixed {
   double ax, ay, az, p;
   __device__ void init() { ax = ay = az = p = 0.0; }
@@ -156,11 +156,12 @@ struct AccF64 {
     const double by = q.bxy * dx + q.byy * dy + q.byz * dz;
     const double bz = q.bxz * dx + q.byz * dy + q.bzz * dz;
     const double dbd = dx * bx + dy * by + dz * bz;
-    const double g = 7.5 * dbd * ri7 - 1.5 * q.T * ri5;
+    const double T = 2.0 * q.t05;
+    const double g = 7.5 * dbd * ri7 - 1.5 * T * ri5;
     ax += m * ri3 * dx - 3.0 * ri5 * bx + g * dx;
     ay += m * ri3 * dy - 3.0 * ri5 * by + g * dy;
     az += m * ri3 * dz - 3.0 * ri5 * bz + g * dz;
-    p += -m * ri + 0.5 * (q.T * ri3 - 3.0 * dbd * ri5);
+    p += -m * ri + 0.5 * (T * ri3 - 3.0 * dbd * ri5);
   }
 };
 
@@ -170,8 +171,8 @@ __device__ __forceinline__ QuadRec quad_load(const QuadRec* base, int c) {
   const __attribute__((address_space(4))) QuadRec* p =
       (const __attribute__((address_space(4))) QuadRec*)(uintptr_t)base + (uint32_t)c;
   QuadRec r;
-  r.bxx = p->bxx; r.bxy = p->bxy; r.bxz = p->bxz; r.byy = p->byy; r.byz = p->byz; r.bzz = p->bzz; r.T = p->T;
-  r.pad = 0.0;
+  r.bxx = p->bxx; r.bxy = p->bxy; r.bxz = p->bxz; r.byy = p->byy; r.byz = p->byz; r.bzz = p->bzz;
+  r.t05 = p->t05; r.nt15 = p->nt15;
   return r;
 }
 
@@ -460,7 +461,12 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
     if (m_use) {
     R tm;
     if constexpr (kF64) tm = (R)cur.M; else tm = (R)cur.M32;
-    const bool cell = (cur.meta & 1) == 0;
+    // (the walk copies mark a leaf by S = 0, resp. l = 0, so their steps need
+    // no meta word to tell cells from leaves)
+    bool cell;
+    if constexpr (std::is_same<Rec, WalkNode>::value) cell = __builtin_bit_cast(uint64_t, cur.S) != 0;
+    else if constexpr (std::is_same<Rec, ThetaNode>::value) cell = __builtin_bit_cast(uint64_t, cur.l) != 0;
+    else cell = (cur.meta & 1) == 0;
     // FP32: the term's factors are formed for every lane ahead of the masked
     // sums (a VALU instruction costs the same with lanes masked off), so
     // that they overlap the cursor's scalar work instead of following it.

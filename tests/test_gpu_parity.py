@@ -361,3 +361,30 @@ def test_fp64_walk_full_size(bh):
     acc, pot, w = _walk_compare(bh, pos, mass, "fp64", 0.5, spec["eps"], targets=tg)
     check_forces(acc, w["acc"], w["amag"], F64_TOL, "plummer1m fp64", log=say)
     assert pot_err(pot, w["pot"]).max() <= F64_TOL
+
+
+@pytest.mark.parametrize("b,prec", [(1, "fp32"), (2, "fp32"), (3, "fp64"), (4, "fp32"), (5, "fp64")])
+def test_hilbert_walk_order_on_a_lattice(bh, b, prec):
+    """One particle in each cell of the 2^b grid of the root cube: the Hilbert target order visits
+    every particle once, and consecutive targets sit in face-adjacent cells (the defining property
+    of a Hilbert curve, which no Morton or row-major order has).  The Morton order is checked to
+    fail it."""
+    say(f"[hilbert] lattice 2^{b} per axis, {prec}")
+    k = 1 << b
+    g = (np.arange(k) + 0.5) / k
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(b)
+    perm = rng.permutation(len(pos))
+    pos = pos[perm]
+    mass = np.full(len(pos), 1.0 / len(pos))
+    T = bh.Tree(*_gpu(pos, mass, prec))
+    idx = (np.floor(pos * k)).astype(np.int64)
+    for order, adjacent in ((2, True), (0, False)):
+        T.set_walk_config(target_order=order)
+        w = T.walk_order().cpu().numpy().astype(np.int64)
+        assert np.array_equal(np.sort(w), np.arange(len(pos)))
+        steps = np.abs(np.diff(idx[w], axis=0)).sum(1)
+        if adjacent:
+            assert np.all(steps == 1), (order, np.unique(steps))
+        else:
+            assert steps.max() > 1

@@ -59,15 +59,17 @@ def test_kepler_two_body_matches_oracle(bh):
     assert np.linalg.norm(sep - (pos[0] - pos[1])) < 2e-3
 
 
-def test_plummer_steps_match_oracle_at_small_theta(bh):
-    say("[step] Plummer 2k FP64, theta 0.01 (every term a particle term), 20 steps")
+def test_plummer_steps_match_oracle_at_tiny_theta(bh):
+    say("[step] Plummer 2k FP64, theta 1e-7 (every term a particle term), 20 steps")
     pos, mass = inputs.plummer(2048, 21)
     rng = np.random.default_rng(5)
     vel = 0.3 * rng.normal(size=pos.shape)
-    P, V, Mt, A, U = _state(bh, pos, vel, mass, torch.float64, 0.01, 0.01)
+    # (theta 1e-7: a cell of side l could only be accepted beyond l / theta, more than 100 times the
+    # smallest side of 2^-21 of the root cube: farther than any particle)
+    P, V, Mt, A, U = _state(bh, pos, vel, mass, torch.float64, 1e-7, 0.01)
     ws = None
     for _ in range(20):
-        ws = bh.leapfrog_step(P, V, Mt, A, U, 1e-3, 0.01, 0.01, workspace=ws)
+        ws = bh.leapfrog_step(P, V, Mt, A, U, 1e-3, 1e-7, 0.01, workspace=ws)
     torch.cuda.synchronize()
     po, vo, ao, uo = oracle.leapfrog(pos, vel, mass, 0.01, 1e-3, 20)
     # the walk sums in depth-first order, the oracle in index order: rounding-level differences per
