@@ -24,7 +24,11 @@ import torch  # noqa: E402
 
 METRIC = "particle-interactions/s and forces/s at RMS rel force err 1e-3, N=4M, 1 GPU"
 FLOPS_PER_INTERACTION = 38          # the paper's conventional count (Sec. 3)
-PEAK_FP32_TFLOPS = 157.3            # MI355X FP32 vector peak
+# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP64 and for
+# unpacked FP32 -- the instructions the walk issues (FP64 offsets, tests and sums, unpacked FP32
+# terms); packed FP32 doubles the FP32 rate to 157.3 TFLOP/s, which this code does not use.
+PEAK_VALU_TFLOPS = 78.6
+PEAK_PACKED_FP32_TFLOPS = 157.3
 
 
 def log(*a):
@@ -352,6 +356,95 @@ def cube_bench(args, bh, inputs):
     print(json.dumps(line), flush=True)
 
 
+def quad_steps(args, bh, inputs, gpos, gmass, ws, acc, pot, eps, n, ref):
+    """The same step with order-2 cell terms (quadrupole) at --quad-theta: build + second moments +
+    walk, timed like the headline; RMS error on the same sampled targets; interactions counted."""
+    theta = args.quad_theta
+
+    def make():
+        T = bh.Tree(gpos, gmass, workspace=ws)
+        T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share, args.persistent,
+                          args.targets_per_lane)
+        T.set_order(2)
+        return T
+
+    for _ in range(args.warmup):
+        make().forces(theta, eps, acc=acc, pot=pot)
+    T = make()
+    st = T.walk_stats(theta, eps)
+    inter = int(st["counts"].to(torch.int64).sum().item())
+    del st, T
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    trees = []
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        T = make()
+        T.set_timing(True)
+        T.forces(theta, eps, acc=acc, pot=pot)
+        trees.append(T)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    walk = float(np.mean([T.walk_time_ms() for T in trees]))
+    del trees
+    rms = None
+    if ref is not None:
+        from paper_1112_4539_amd import metrics
+        T = make()
+        a, _ = T.forces(theta, eps, acc=acc, pot=pot)
+        rms = metrics.rms_rel_err(a[ref[0]], ref[1])
+    log(f"[bench] quadrupole theta={theta}: ms/step={ms:.3f} walk {walk:.3f} ms, interactions {inter}, RMS {rms}")
+    return {"theta": theta, "rms_rel_force_err": rms, "interactions_per_step": inter, "ms_per_step": ms,
+            "walk_ms": walk, "forces_per_s": n / (ms * 1e-3), "interactions_per_s": inter / (ms * 1e-3)}
+
+
+def leapfrog_bench(args, bh, inputs):
+    """The time loop on the clumpy field N=4,194,304 (FP32, theta --theta, eps 1e-4): kick-drift-kick
+    leapfrog steps with a tree rebuild each step, with the state kept in the caller's (random) order
+    and with it permuted into each new tree's Morton order (Sec. 5: the order comes for free)."""
+    pos, mass, spec = inputs.make("clumpy4m")
+    eps, theta, dt = spec["eps"], args.theta, 1e-5
+    n = len(pos)
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(9)
+    vel0 = 0.01 * rng.normal(size=pos.shape)
+    ws = torch.empty(bh.workspace_bytes(n, bh.FP32), dtype=torch.uint8, device=dev)
+    res = {}
+    for reorder in (False, True):
+        P = torch.tensor(pos.astype(np.float32), device=dev)
+        V = torch.tensor(vel0.astype(np.float32), device=dev)
+        M = torch.tensor(mass.astype(np.float32), device=dev)
+        A, U = bh.Tree(P, M, workspace=ws).forces(theta, eps)
+        A, U = A.clone(), U.clone()
+        for _ in range(args.warmup):
+            bh.leapfrog_step(P, V, M, A, U, dt, theta, eps, reorder=reorder, workspace=ws)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(args.steps):
+            bh.leapfrog_step(P, V, M, A, U, dt, theta, eps, reorder=reorder, workspace=ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        # build alone on the state as it now stands (caller order, or the last Morton order)
+        ev0.record()
+        for _ in range(args.steps):
+            bh.Tree(P, M, workspace=ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        res["morton_reorder" if reorder else "caller_order"] = {
+            "ms_per_step": ms, "steps_per_s": 1e3 / ms, "build_ms": ev0.elapsed_time(ev1) / args.steps}
+        log(f"[bench] leapfrog reorder={reorder}: {res}")
+    line = {"metric": "leapfrog steps/s (build + walk + kicks each step), clumpy N=4M",
+            "value": res["morton_reorder"]["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["morton_reorder"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, eps={eps}, theta={theta}, dt={dt}, "
+                                   "FP32 state, velocities N(0, 0.01)", "modes": res}}
+    print(json.dumps(line), flush=True)
+
+
 def walk_only(args, bh, inputs):
     """One build and WALK_ONLY force walks of a named workload, nothing else: the command that
     the rocprofv3 counter and trace summaries are taken from (target order, expansion order and
@@ -390,6 +483,8 @@ def main():
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--targets-per-lane", type=int, default=1)
     ap.add_argument("--order", type=int, default=1, help="cell terms: 1 monopole, 2 with the quadrupole")
+    ap.add_argument("--quad-theta", type=float, default=0.59,
+                    help="also time the quadrupole step at this theta (0: skip)")
     ap.add_argument("--walk-only", type=int, default=0, metavar="K",
                     help="only build once and run K force walks of --workload (for profiler runs)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -414,6 +509,8 @@ def main():
         return learned_bench(args, bh, inputs)
     if args.workload == "cube1m":
         return cube_bench(args, bh, inputs)
+    if args.workload == "leapfrog":
+        return leapfrog_bench(args, bh, inputs)
 
     if args.copy_calib > 0:
         # a plain copy of known size: reads and writes exactly MIB MiB each
@@ -501,6 +598,11 @@ def main():
         rms = metrics.rms_rel_err(a[tg], a_ref)
         log(f"[bench] RMS rel force err vs FP64 direct on {args.samples} targets: {rms:.3e}")
 
+    quad = None
+    if args.quad_theta > 0:
+        quad = quad_steps(args, bh, inputs, gpos, gmass, ws, acc, pot, eps, n, None if rms is None else (tg, a_ref))
+        quad["forces_per_s_vs_monopole"] = quad["forces_per_s"] / (n / (ms_step * 1e-3))
+
     value = inter / (ms_step * 1e-3)
     achieved = FLOPS_PER_INTERACTION * inter / (walk_avg * 1e-3) / 1e12
     line = {
@@ -514,9 +616,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
+            "precision": "FP32 positions, masses and outputs; FP32 terms (r^2+eps^2 rounded once, v_rsq_f32, FP32 "
+                         "products); FP64 offsets, opening test and sums",
             "workload": f"clumpy field N={n} (25% uniform in the unit cube + 64 Plummer clumps a=0.01, R=0.1), "
                         f"seed {spec['seed']}, eps={eps}, theta={args.theta}, FP32 in/out",
             "n": n, "theta": args.theta, "eps": eps,
@@ -526,16 +630,19 @@ def main():
             "walk_interactions_per_s": inter / (walk_avg * 1e-3),
             "rms_rel_force_err": rms, "accuracy_targets": None if rms is None else args.samples,
             "n_nodes": tstats["n_nodes"],
+            "quadrupole": quad,
             "launch": {"waves_per_block": args.waves_per_block, "xcd_chunk": args.xcd_chunk,
                        "target_order": args.target_order, "lds_share": args.lds_share,
                        "persistent": args.persistent, "targets_per_lane": args.targets_per_lane},
         },
         "roofline": {
-            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
+            "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_VALU_TFLOPS,
             "traffic": measured_traffic(args.workload, args.theta),
             "kernel": "bh::k_walk<false, 1, 0, true, false>", "flops_per_unit": FLOPS_PER_INTERACTION,
             "units_per_launch": inter,
+            "peak_note": "FP64 and unpacked FP32 vector rate; packed FP32 peak 157.3 TFLOP/s",
+            "frac_of_packed_fp32_peak": achieved / PEAK_PACKED_FP32_TFLOPS,
         },
         "cpu_baseline": None,
     }
