@@ -115,13 +115,16 @@ size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_
   t.ilevel = reinterpret_cast<int32_t*>(take(4 * N));
   t.ifirst = reinterpret_cast<int32_t*>(take(4 * N));
   t.ilast = reinterpret_cast<int32_t*>(take(4 * N));
-  t.ipre = reinterpret_cast<int32_t*>(take(4 * N));
   t.nstart = reinterpret_cast<int32_t*>(take(4 * (N + 1)));
   t.nexcl = reinterpret_cast<int32_t*>(take(4 * (N + 1)));
   t.lmask = reinterpret_cast<uint32_t*>(take(4 * (N + 1)));
   t.nodes = reinterpret_cast<bh::Node*>(take(sizeof(bh::Node) * nodes));
   t.mom = reinterpret_cast<bh::Mom*>(take(sizeof(bh::Mom) * nodes));
   t.nx = reinterpret_cast<int32_t*>(take(4 * nodes));
+  t.nlev = reinterpret_cast<uint8_t*>(take(nodes));
+  t.ocnt = reinterpret_cast<int32_t*>(take(4 * bh::kLevels));
+  t.obkt = reinterpret_cast<int32_t*>(take(4 * bh::kLevels * (size_t)bh::n_chunks((int64_t)N)));
+  t.okids = reinterpret_cast<int32_t*>(take(32 * bh::kLevels * (size_t)bh::n_chunks((int64_t)N)));
   // (one spare record past the last: the walk reads the record after its
   // cursor's last position before it tests the loop bound)
   t.wnodes = reinterpret_cast<bh::WalkNode*>(take(sizeof(bh::WalkNode) * (nodes + 1)));

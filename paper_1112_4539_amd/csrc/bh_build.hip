@@ -683,18 +683,23 @@ __global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict
                                                         const int32_t* __restrict__ nexcl,
                                                         const uint32_t* __restrict__ lmask,
                                                         const int32_t* __restrict__ ustart,
-                                                        int32_t* __restrict__ ipre, Node* __restrict__ nodes,
-                                                        int32_t* __restrict__ nx, int nmax) {
+                                                        const uint64_t* __restrict__ ukey, Node* __restrict__ nodes,
+                                                        int32_t* __restrict__ nx, uint8_t* __restrict__ nlev,
+                                                        int nmax) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nmax || v >= cnt->n_internal) return;
   const int s = ilevel[v], f = ifirst[v], l = ilast[v];
   const int pre = f + nexcl[f] + __popc(lmask[f] & ((1u << s) - 1u));
-  ipre[v] = pre;
   const Cube* cube = cubes + (ucid ? ucid[f] : 0);
   Node nd;
-  nd.cx = nd.cy = nd.cz = 0.0;
-  nd.M = 0.0;
   nd.l = ldexp(cube->L, -s);
+  // the cube's centre, in the centre-of-mass fields until the moment passes
+  // replace it (they need it for s, and for the centre of a massless cell)
+  const uint64_t prefix = (s == 0) ? 0ull : (ukey[f] >> (63 - 3 * s));
+  nd.cx = cube->lo[0] + ((double)compact3(prefix >> 2) + 0.5) * nd.l;
+  nd.cy = cube->lo[1] + ((double)compact3(prefix >> 1) + 0.5) * nd.l;
+  nd.cz = cube->lo[2] + ((double)compact3(prefix) + 0.5) * nd.l;
+  nd.M = 0.0;
   nd.s = 0.0;
   nd.next = l + nexcl[l] + nstart[l] + 1;
   nd.first = ustart[f];
@@ -702,6 +707,7 @@ __global__ __launch_bounds__(256) void k_nodes_internal(const Counts* __restrict
   nd.meta = s << 8;
   nodes[pre] = nd;
   nx[pre] = nd.next;
+  nlev[pre] = (uint8_t)s;
 }
 
 template <typename T4>
@@ -712,7 +718,7 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
                                                     const int32_t* __restrict__ nexcl,
                                                     const int32_t* __restrict__ ustart, const T4* __restrict__ ps,
                                                     Node* __restrict__ nodes, Mom* __restrict__ mom,
-                                                    int32_t* __restrict__ nx, int nmax) {
+                                                    int32_t* __restrict__ nx, uint8_t* __restrict__ nlev, int nmax) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int U = cnt->n_unique;
   if (x >= nmax || x >= U) return;
@@ -774,46 +780,84 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
   nodes[pre] = nd;
   mom[pre] = Mom{M, X, Y, Z};
   nx[pre] = pre + 1;
+  nlev[pre] = (uint8_t)level;
 }
 
-// Moments of the internal nodes of one level (children are deeper, so they are
-// final).  Children are pre+1, next(pre+1), ... < next(pre), in octant order.
-// The chain and the sums read the compact next array and the 32-byte moment
-// records rather than the 64-byte nodes.
-__global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict__ cnt, const Cube* __restrict__ cubes,
-                                                       const int32_t* __restrict__ ucid,
-                                                       const int32_t* __restrict__ ilevel,
-                                                       const int32_t* __restrict__ ifirst,
-                                                       const int32_t* __restrict__ ipre,
-                                                       const uint64_t* __restrict__ ukey, Node* __restrict__ nodes,
-                                                       Mom* __restrict__ mom, const int32_t* __restrict__ nx,
-                                                       int level, int nmax) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nmax || v >= cnt->n_internal || ilevel[v] != level) return;
-  const int p = ipre[v];
-  const Cube* cube = cubes + (ucid ? ucid[ifirst[v]] : 0);
-  const int n_nodes = cnt->n_nodes;
-  const int end = min(nx[p], n_nodes);
-  double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
-  // at most 8 children; the bound also keeps a corrupted record from looping
-  int c = p + 1;
-  for (int k = 0; k < 8 && c < end; ++k, c = max(nx[c], c + 1)) {
-    const Mom q = mom[c];
-    M += q.M;
-    X += q.X;
-    Y += q.Y;
-    Z += q.Z;
+// ---------------------------------------------------------------- moments
+// The moments of an internal node fold its children's, in octant order (the
+// preorder of the children p+1, next(p+1), ... < next(p)).  The fold runs
+// bottom-up in two launches, with the same arithmetic for every node:
+//  * k_moments_chunk: a workgroup loads a chunk of kChunk consecutive preorder
+//    nodes (next, level, the leaves' moments) into LDS and folds there, level
+//    by level (deepest first), every internal node whose subtree ends inside
+//    the chunk.  The others, at most one per level, are put in their level's
+//    list together with their children (read along next, past the chunk's
+//    end from memory);
+//  * k_moments_top: one launch per level folds that level's listed nodes
+//    from their children's records in memory.
+// A node's children are deeper than it, so each fold reads finished values.
+
+// Per-chunk index in LDS: next of every node, and the internal nodes whose
+// subtree ends in the chunk grouped by level.
+struct ChunkIndex {
+  int32_t nx[kChunk];
+  int16_t ord[kChunk];         // chunk offsets of the closed internal nodes, by level
+  uint8_t lv[kChunk];
+  int32_t start[kLevels + 2];  // ord range of each level
+  int32_t fill[kLevels + 1];
+  int32_t levels[kLevels + 1]; // the levels that have closed internal nodes, deepest first
+  int32_t n_levels;
+};
+
+__device__ __forceinline__ bool chunk_leaf(const ChunkIndex& ci, int c0, int i) { return ci.nx[i] == c0 + i + 1; }
+
+// Groups the chunk's closed internal nodes by level (ci.nx and ci.lv loaded,
+// then a barrier, by the caller).  Ends with a barrier.
+__device__ void chunk_sort(ChunkIndex& ci, int c0, int cn) {
+  const int tid = threadIdx.x, c1 = c0 + cn;
+  if (tid <= kLevels) ci.fill[tid] = 0;
+  __syncthreads();
+  for (int i = tid; i < cn; i += blockDim.x)
+    if (!chunk_leaf(ci, c0, i) && ci.nx[i] <= c1) atomicAdd(&ci.fill[ci.lv[i]], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0, nl = 0;
+    for (int L = 0; L <= kLevels; ++L) {
+      ci.start[L] = acc;
+      acc += ci.fill[L];
+    }
+    ci.start[kLevels + 1] = acc;
+    for (int L = kLevels; L >= 0; --L)
+      if (ci.fill[L]) ci.levels[nl++] = L;
+    ci.n_levels = nl;
   }
-  const double l = nodes[p].l;
-  const uint64_t prefix = (level == 0) ? 0ull : (ukey[ifirst[v]] >> (63 - 3 * level));
-  const double ctr[3] = {cube->lo[0] + ((double)compact3(prefix >> 2) + 0.5) * l,
-                         cube->lo[1] + ((double)compact3(prefix >> 1) + 0.5) * l,
-                         cube->lo[2] + ((double)compact3(prefix) + 0.5) * l};
+  __syncthreads();
+  if (tid <= kLevels) ci.fill[tid] = 0;
+  __syncthreads();
+  for (int i = tid; i < cn; i += blockDim.x) {
+    if (chunk_leaf(ci, c0, i) || ci.nx[i] > c1) continue;
+    const int L = ci.lv[i];
+    ci.ord[ci.start[L] + atomicAdd(&ci.fill[L], 1)] = (int16_t)i;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void add_mom(Mom& s, const Mom& q) {
+  s.M += q.M;
+  s.X += q.X;
+  s.Y += q.Y;
+  s.Z += q.Z;
+}
+
+// Centre of mass and s of node p from its folded moments q; the node record
+// holds its cube's centre until here.
+__device__ __forceinline__ void finish_node(int p, const Mom& q, Node* __restrict__ nodes, Mom* __restrict__ mom) {
+  const double ctr[3] = {nodes[p].cx, nodes[p].cy, nodes[p].cz};
   double com[3];
-  if (M != 0.0) {
-    com[0] = X / M;
-    com[1] = Y / M;
-    com[2] = Z / M;
+  if (q.M != 0.0) {
+    com[0] = q.X / q.M;
+    com[1] = q.Y / q.M;
+    com[2] = q.Z / q.M;
   } else {
     com[0] = ctr[0];
     com[1] = ctr[1];
@@ -823,9 +867,84 @@ __global__ __launch_bounds__(256) void k_moments_level(const Counts* __restrict_
   nodes[p].cx = com[0];
   nodes[p].cy = com[1];
   nodes[p].cz = com[2];
-  nodes[p].M = M;
+  nodes[p].M = q.M;
   nodes[p].s = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-  mom[p] = Mom{M, X, Y, Z};
+  mom[p] = q;
+}
+
+__global__ __launch_bounds__(256) void k_moments_chunk(const Counts* __restrict__ cnt, const int32_t* __restrict__ nx,
+                                                       const uint8_t* __restrict__ nlev, Node* __restrict__ nodes,
+                                                       Mom* __restrict__ mom, int32_t* __restrict__ ocnt,
+                                                       int32_t* __restrict__ obkt, int32_t* __restrict__ okids,
+                                                       int nchunks) {
+  __shared__ ChunkIndex ci;
+  __shared__ Mom sm[kChunk];
+  const int n_nodes = cnt->n_nodes;
+  const int c0 = blockIdx.x * kChunk;
+  if (c0 >= n_nodes) return;
+  const int cn = min(kChunk, n_nodes - c0), c1 = c0 + cn;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < cn; i += blockDim.x) {
+    const int nxt = nx[c0 + i];
+    ci.nx[i] = nxt;
+    ci.lv[i] = (uint8_t)min((int)nlev[c0 + i], kLevels);
+    if (nxt == c0 + i + 1) sm[i] = mom[c0 + i];  // a leaf
+  }
+  __syncthreads();
+  chunk_sort(ci, c0, cn);
+  for (int t = 0; t < ci.n_levels; ++t) {
+    const int L = ci.levels[t];
+    for (int j = ci.start[L] + tid; j < ci.start[L + 1]; j += blockDim.x) {
+      const int i = ci.ord[j];
+      const int end = ci.nx[i] - c0;
+      Mom q{0.0, 0.0, 0.0, 0.0};
+      int c = i + 1;
+      for (int k = 0; k < 8 && c < end; ++k, c = max(ci.nx[c] - c0, c + 1)) add_mom(q, sm[c]);
+      sm[i] = q;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < cn; i += blockDim.x) {
+    if (chunk_leaf(ci, c0, i)) continue;
+    if (ci.nx[i] <= c1) {
+      finish_node(c0 + i, sm[i], nodes, mom);
+      continue;
+    }
+    // crosses the chunk's end: list it with its children (past the end, the
+    // chain of next continues in memory)
+    const int L = ci.lv[i];
+    const int slot = min(atomicAdd(ocnt + L, 1), nchunks - 1) + L * nchunks;
+    obkt[slot] = c0 + i;
+    const int end = min(ci.nx[i], n_nodes);
+    int c = c0 + i + 1, k = 0;
+    for (; k < 8 && c < end; ++k) {
+      okids[8 * slot + k] = c;
+      c = max(c < c1 ? ci.nx[c - c0] : nx[c], c + 1);
+    }
+    for (; k < 8; ++k) okids[8 * slot + k] = -1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_moments_top(const Counts* __restrict__ cnt, const int32_t* __restrict__ ocnt,
+                                                     const int32_t* __restrict__ obkt,
+                                                     const int32_t* __restrict__ okids, int nchunks,
+                                                     Node* __restrict__ nodes, Mom* __restrict__ mom, int L) {
+  const int n_nodes = cnt->n_nodes;
+  {
+    const int m = min(ocnt[L], nchunks);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+      const int slot = L * nchunks + j;
+      const int p = obkt[slot];
+      if (p < 0 || p >= n_nodes) continue;
+      Mom q{0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < 8; ++k) {
+        const int c = okids[8 * slot + k];
+        if (c <= p || c >= n_nodes) break;
+        add_mom(q, mom[c]);
+      }
+      finish_node(p, q, nodes, mom);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- driver
@@ -902,12 +1021,18 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
   if ((e = scan_excl(w.nstart, w.nexcl, n + 1, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
   k_croot_final<<<nblk(K + 1, 256), 256, 0, st>>>(K, w.nexcl, w.croot);
   k_nodes_internal<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.ilevel, w.ifirst, w.ilast,
-                                                     w.nstart, w.nexcl, w.lmask, w.ustart, w.ipre, w.nodes, w.nx, n);
+                                                     w.nstart, w.nexcl, w.lmask, w.ustart, w.ukey, w.nodes, w.nx,
+                                                     w.nlev, n);
   k_nodes_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.split, w.nstart, w.nexcl, w.ustart,
-                                                 reinterpret_cast<const T4*>(w.ps), w.nodes, w.mom, w.nx, n);
-  for (int level = kLevels - 1; level >= 0; --level)
-    k_moments_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.cube, ucid, w.ilevel, w.ifirst, w.ipre, w.ukey,
-                                                  w.nodes, w.mom, w.nx, level, n);
+                                                 reinterpret_cast<const T4*>(w.ps), w.nodes, w.mom, w.nx, w.nlev, n);
+  // moments: chunks of the preorder (2n nodes at most), then the straddling
+  // internal nodes
+  const int nch = (int)n_chunks(n);
+  k_fill_i32<<<1, 64, 0, st>>>(w.ocnt, kLevels, 0);
+  k_moments_chunk<<<nch, 256, 0, st>>>(w.counts, w.nx, w.nlev, w.nodes, w.mom, w.ocnt, w.obkt, w.okids, nch);
+  const int tg = nblk(nch, 256);
+  for (int L = kLevels - 1; L >= 0; --L)
+    k_moments_top<<<tg, 256, 0, st>>>(w.counts, w.ocnt, w.obkt, w.okids, nch, w.nodes, w.mom, L);
   return hipGetLastError();
 }
 
@@ -1068,66 +1193,124 @@ __device__ __forceinline__ void put_quad(QuadRec* __restrict__ qr, int p, const 
   qr[p] = q;
 }
 
+// Second moments of leaf c (over its particles; one particle: zero).
 template <typename T4>
-__global__ __launch_bounds__(256) void k_quad_leaf(const Counts* __restrict__ cnt, const int32_t* __restrict__ nstart,
-                                                   const int32_t* __restrict__ nexcl, const int32_t* __restrict__ ustart,
-                                                   const T4* __restrict__ ps, const Node* __restrict__ nodes,
-                                                   QuadRec* __restrict__ qr, int nmax) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= nmax || x >= cnt->n_unique) return;
-  const int pre = x + nexcl[x] + nstart[x];
-  const int first = ustart[x], count = ustart[x + 1] - first;
-  double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (count > 1) {
-    const Node nd = nodes[pre];
-    for (int k = first; k < first + count; ++k) {
-      const T4 q = ps[k];
-      const double m = (double)q.w;
-      const double y0 = (double)q.x - nd.cx, y1 = (double)q.y - nd.cy, y2 = (double)q.z - nd.cz;
-      b[0] += m * y0 * y0;
-      b[1] += m * y0 * y1;
-      b[2] += m * y0 * y2;
-      b[3] += m * y1 * y1;
-      b[4] += m * y1 * y2;
-      b[5] += m * y2 * y2;
-    }
+__device__ __forceinline__ void leaf_quad(const Node& nd, const T4* __restrict__ ps, double b[6]) {
+  for (int t = 0; t < 6; ++t) b[t] = 0.0;
+  if (nd.count <= 1) return;
+  for (int k = nd.first; k < nd.first + nd.count; ++k) {
+    const T4 q = ps[k];
+    const double m = (double)q.w;
+    const double y0 = (double)q.x - nd.cx, y1 = (double)q.y - nd.cy, y2 = (double)q.z - nd.cz;
+    b[0] += m * y0 * y0;
+    b[1] += m * y0 * y1;
+    b[2] += m * y0 * y2;
+    b[3] += m * y1 * y1;
+    b[4] += m * y1 * y2;
+    b[5] += m * y2 * y2;
   }
-  put_quad(qr, pre, b);
 }
 
-__global__ __launch_bounds__(256) void k_quad_level(const Counts* __restrict__ cnt, const int32_t* __restrict__ ilevel,
-                                                    const int32_t* __restrict__ ipre, const Node* __restrict__ nodes,
-                                                    const int32_t* __restrict__ nx, QuadRec* __restrict__ qr, int level,
-                                                    int nmax) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nmax || v >= cnt->n_internal || ilevel[v] != level) return;
-  const int p = ipre[v];
-  const int end = min(nx[p], cnt->n_nodes);
-  const Node np = nodes[p];
-  double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int c = p + 1;
-  for (int k = 0; k < 8 && c < end; ++k, c = max(nx[c], c + 1)) {
-    const Node nc = nodes[c];
-    const QuadRec q = qr[c];
-    const double d0 = nc.cx - np.cx, d1 = nc.cy - np.cy, d2 = nc.cz - np.cz;
-    const double m0 = nc.M * d0, m1 = nc.M * d1, m2 = nc.M * d2;
-    b[0] += q.bxx + m0 * d0;
-    b[1] += q.bxy + m0 * d1;
-    b[2] += q.bxz + m0 * d2;
-    b[3] += q.byy + m1 * d1;
-    b[4] += q.byz + m1 * d2;
-    b[5] += q.bzz + m2 * d2;
+// Child c's term of the parallel-axis fold into a parent with centre of mass
+// (px, py, pz).
+__device__ __forceinline__ void quad_fold(double b[6], const double cb[6], double cx, double cy, double cz, double cM,
+                                          double px, double py, double pz) {
+  const double d0 = cx - px, d1 = cy - py, d2 = cz - pz;
+  const double m0 = cM * d0, m1 = cM * d1, m2 = cM * d2;
+  b[0] += cb[0] + m0 * d0;
+  b[1] += cb[1] + m0 * d1;
+  b[2] += cb[2] + m0 * d2;
+  b[3] += cb[3] + m1 * d1;
+  b[4] += cb[4] + m1 * d2;
+  b[5] += cb[5] + m2 * d2;
+}
+
+// The two launches of the first moments (k_moments_chunk, k_moments_top), for
+// the second, over the same chunks: the chunk launch forms the leaves' moments
+// from their particles and folds the chunk's closed nodes in LDS; the
+// straddling nodes and their children are the lists the build made.
+template <typename T4>
+__global__ __launch_bounds__(1024) void k_quad_chunk(const Counts* __restrict__ cnt, const int32_t* __restrict__ nx,
+                                                    const uint8_t* __restrict__ nlev, const Node* __restrict__ nodes,
+                                                    const T4* __restrict__ ps, QuadRec* __restrict__ qr) {
+  __shared__ ChunkIndex ci;
+  __shared__ double sb[kChunk][6];
+  __shared__ double sc[kChunk][4];
+  const int n_nodes = cnt->n_nodes;
+  const int c0 = blockIdx.x * kChunk;
+  if (c0 >= n_nodes) return;
+  const int cn = min(kChunk, n_nodes - c0), c1 = c0 + cn;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < cn; i += blockDim.x) {
+    const int nxt = nx[c0 + i];
+    const Node nd = nodes[c0 + i];
+    ci.nx[i] = nxt;
+    ci.lv[i] = (uint8_t)min((int)nlev[c0 + i], kLevels);
+    sc[i][0] = nd.cx;
+    sc[i][1] = nd.cy;
+    sc[i][2] = nd.cz;
+    sc[i][3] = nd.M;
+    if (nxt == c0 + i + 1) {
+      double b[6];
+      leaf_quad(nd, ps, b);
+      for (int t = 0; t < 6; ++t) sb[i][t] = b[t];
+      put_quad(qr, c0 + i, b);
+    }
   }
-  put_quad(qr, p, b);
+  __syncthreads();
+  chunk_sort(ci, c0, cn);
+  for (int t = 0; t < ci.n_levels; ++t) {
+    const int L = ci.levels[t];
+    for (int j = ci.start[L] + tid; j < ci.start[L + 1]; j += blockDim.x) {
+      const int i = ci.ord[j];
+      const int end = ci.nx[i] - c0;
+      double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int c = i + 1;
+      for (int k = 0; k < 8 && c < end; ++k, c = max(ci.nx[c] - c0, c + 1))
+        quad_fold(b, sb[c], sc[c][0], sc[c][1], sc[c][2], sc[c][3], sc[i][0], sc[i][1], sc[i][2]);
+      for (int t = 0; t < 6; ++t) sb[i][t] = b[t];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < cn; i += blockDim.x)
+    if (!chunk_leaf(ci, c0, i) && ci.nx[i] <= c1) put_quad(qr, c0 + i, sb[i]);
+}
+
+__global__ __launch_bounds__(256) void k_quad_top(const Counts* __restrict__ cnt, const int32_t* __restrict__ ocnt,
+                                                  const int32_t* __restrict__ obkt, const int32_t* __restrict__ okids,
+                                                  int nchunks, const Node* __restrict__ nodes,
+                                                  QuadRec* __restrict__ qr, int L) {
+  const int n_nodes = cnt->n_nodes;
+  {
+    const int m = min(ocnt[L], nchunks);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+      const int slot = L * nchunks + j;
+      const int p = obkt[slot];
+      if (p < 0 || p >= n_nodes) continue;
+      const Node np = nodes[p];
+      double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < 8; ++k) {
+        const int c = okids[8 * slot + k];
+        if (c <= p || c >= n_nodes) break;
+        const Node nc = nodes[c];
+        const QuadRec q = qr[c];
+        const double cb[6] = {q.bxx, q.bxy, q.bxz, q.byy, q.byz, q.bzz};
+        quad_fold(b, cb, nc.cx, nc.cy, nc.cz, nc.M, np.cx, np.cy, np.cz);
+      }
+      put_quad(qr, p, b);
+    }
+  }
 }
 
 template <typename T4>
 static hipError_t quad_impl(int n, const BuildWs& w, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  k_quad_leaf<T4><<<nblk(n, 256), 256, 0, st>>>(w.counts, w.nstart, w.nexcl, w.ustart,
-                                                reinterpret_cast<const T4*>(w.ps), w.nodes, w.qrec, n);
-  for (int level = kLevels - 1; level >= 0; --level)
-    k_quad_level<<<nblk(n, 256), 256, 0, st>>>(w.counts, w.ilevel, w.ipre, w.nodes, w.nx, w.qrec, level, n);
+  const int nch = (int)n_chunks(n);
+  // (87 KB of LDS: one workgroup per CU, so it brings 16 waves)
+  k_quad_chunk<T4><<<nch, 1024, 0, st>>>(w.counts, w.nx, w.nlev, w.nodes, reinterpret_cast<const T4*>(w.ps), w.qrec);
+  const int tg = nblk(nch, 256);
+  for (int L = kLevels - 1; L >= 0; --L)
+    k_quad_top<<<tg, 256, 0, st>>>(w.counts, w.ocnt, w.obkt, w.okids, nch, w.nodes, w.qrec, L);
   return hipGetLastError();
 }
 

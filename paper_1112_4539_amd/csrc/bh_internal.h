@@ -26,6 +26,14 @@ struct alignas(32) Mom {
 // the clusters one after the other in Morton order, so every cluster keeps its
 // particle range, and its subtree is the preorder node range [croot[k],
 // croot[k+1]).  A single tree is the forest with K = 1.
+// The moment passes fold every subtree that lies inside one chunk of kChunk
+// consecutive preorder nodes in a workgroup's LDS.  The internal nodes whose
+// subtree crosses the chunk's end are ancestors of the next chunk's first node
+// that start in the chunk, so a chunk has at most one per level: they are kept
+// per level, kLevels x (number of chunks) slots, each with its children.
+constexpr int kChunk = 1024;
+inline int64_t n_chunks(int64_t n) { return (2 * (n > 0 ? n : 1) + kChunk - 1) / kChunk; }
+
 struct BuildWs {
   Cube* cube;               // [K] root cube per cluster
   Counts* counts;
@@ -47,12 +55,16 @@ struct BuildWs {
   uint64_t* ukey;           // [n]
   int32_t* ustart;          // [n + 1]
   int32_t *split, *pf, *pl; // [n]
-  int32_t *ilevel, *ifirst, *ilast, *ipre;  // [n]
+  int32_t *ilevel, *ifirst, *ilast;  // [n]
   int32_t *nstart, *nexcl;  // [n + 1]
   uint32_t* lmask;          // [n + 1]
   Node* nodes;              // [2n]
   Mom* mom;                 // [2n] mass and first moments of every node, for the moment passes
   int32_t* nx;              // [2n] next(c) of every node, for the moment passes
+  uint8_t* nlev;            // [2n] level of every node, for the moment passes
+  int32_t* ocnt;            // [kLevels] straddling internal nodes per level
+  int32_t* obkt;            // [kLevels][n_chunks] the straddling nodes of each level
+  int32_t* okids;           // [kLevels][n_chunks][8] their children in octant order, -1 after the last
   WalkNode* wnodes;         // [2n] walk copy of the nodes for the last uniform theta
   int32_t* horder;          // [n] Morton positions in the Hilbert walk order (filled on demand)
   QuadRec* qrec;            // [2n + 1] second moments of every node (walks of order 2; filled on demand)
