@@ -24,7 +24,8 @@ struct bh_tree {
   const void* pos = nullptr;       // build inputs, kept for graph replays
   const void* mass = nullptr;
   bh::BuildWs w{};
-  int32_t* rank = nullptr;  // caller index -> Morton position
+  int32_t* rank = nullptr;  // caller index -> Morton position (filled on demand)
+  mutable bool rank_ready = false;
   int32_t* queue = nullptr; // group counter of the persistent walk
   int waves_per_block = 1;
   int xcd_chunk = -1;  // -1: 1024 for FP32 trees (about the one-wave workgroups an XCD holds), 0 for FP64
@@ -122,13 +123,17 @@ size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_
   t.mom = reinterpret_cast<bh::Mom*>(take(sizeof(bh::Mom) * nodes));
   t.nx = reinterpret_cast<int32_t*>(take(4 * nodes));
   t.nlev = reinterpret_cast<uint8_t*>(take(nodes));
-  t.ocnt = reinterpret_cast<int32_t*>(take(4 * bh::kLevels));
   t.obkt = reinterpret_cast<int32_t*>(take(4 * bh::kLevels * (size_t)bh::n_chunks((int64_t)N)));
   t.okids = reinterpret_cast<int32_t*>(take(32 * bh::kLevels * (size_t)bh::n_chunks((int64_t)N)));
   // (one spare record past the last: the walk reads the record after its
   // cursor's last position before it tests the loop bound)
   t.wnodes = reinterpret_cast<bh::WalkNode*>(take(sizeof(bh::WalkNode) * (nodes + 1)));
   t.horder = reinterpret_cast<int32_t*>(take(4 * N));
+  t.hkey_a = reinterpret_cast<uint64_t*>(take(8 * N));
+  t.hkey_b = reinterpret_cast<uint64_t*>(take(8 * N));
+  t.hidx = reinterpret_cast<int32_t*>(take(4 * N));
+  t.hhist = reinterpret_cast<int32_t*>(take(4 * hist));
+  t.hscan = reinterpret_cast<int32_t*>(take(4 * scan_tiles));
   t.qrec = reinterpret_cast<bh::QuadRec*>(take(sizeof(bh::QuadRec) * (nodes + 1)));
   int32_t* r = reinterpret_cast<int32_t*>(take(4 * N));
   if (w) *w = t;
@@ -154,17 +159,89 @@ int sync_counts(const bh_tree* t, hipStream_t st, bh::Counts* c) {
   return BH_OK;
 }
 
-hipError_t enqueue_build(const bh_tree* t, hipStream_t st) {
+constexpr int kMaxDevices = 64;
+
+// One second stream per device (default priority), with its two events, for
+// the Hilbert order beside the build; created on first use, kept until the
+// process ends.  Builds that use it hold g_side_mu while they enqueue.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+
+hipError_t side_stream(SideStream** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  SideStream& ss = g_side[dev];
+  if (!ss.s) {
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (b) (void)hipEventDestroy(b);
+      if (a) (void)hipEventDestroy(a);
+      if (s) (void)hipStreamDestroy(s);
+      return e;
+    }
+    ss.s = s;
+    ss.fork = a;
+    ss.join = b;
+  }
+  *out = &ss;
+  return hipSuccess;
+}
+
+hipError_t build_on(const bh_tree* t, const bh::BuildFork* fork, hipStream_t st) {
   const int n = (int)t->n;
+  return t->prec == BH_FP64
+             ? bh::build_tree_f64(static_cast<const double*>(t->pos), static_cast<const double*>(t->mass), n, t->w,
+                                  fork, st)
+             : bh::build_tree_f32(static_cast<const float*>(t->pos), static_cast<const float*>(t->mass), n, t->w,
+                                  fork, st);
+}
+
+// Enqueues the build.  With may_fork, a tree that walks in Hilbert order gets
+// that order formed on the second stream beside the build (not while st is
+// being captured into a graph: the capture then holds the plain sequence).
+hipError_t enqueue_build(const bh_tree* t, hipStream_t st, bool may_fork = true) {
   t->horder_ready = false;
   t->quad_ready = false;
-  hipError_t e = t->prec == BH_FP64
-                     ? bh::build_tree_f64(static_cast<const double*>(t->pos), static_cast<const double*>(t->mass), n,
-                                          t->w, st)
-                     : bh::build_tree_f32(static_cast<const float*>(t->pos), static_cast<const float*>(t->mass), n,
-                                          t->w, st);
-  if (e == hipSuccess && n > 0) e = bh::make_rank(t->w.idx_a, n, t->rank, st);
+  t->rank_ready = false;
+  bool fork = may_fork && t->target_order == 2 && t->n > 0;
+  if (fork) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    fork = hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+  }
+  if (!fork) return build_on(t, nullptr, st);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStream* ss = nullptr;
+  if (side_stream(&ss) != hipSuccess) return build_on(t, nullptr, st);
+  const bh::BuildFork bf{ss->s, ss->fork, ss->join};
+  hipError_t e = build_on(t, &bf, st);
+  if (e == hipSuccess) t->horder_ready = true;
   return e;
+}
+
+// The walk order of the targets for the current build, formed on first use.
+hipError_t ensure_target_order(const bh_tree* t, hipStream_t st) {
+  if (t->n == 0) return hipSuccess;
+  if (t->target_order == 1 && !t->rank_ready) {
+    hipError_t e = bh::make_rank(t->w.idx_a, (int)t->n, t->rank, st);
+    if (e != hipSuccess) return e;
+    t->rank_ready = true;
+  }
+  if (t->target_order == 2 && !t->horder_ready) {
+    hipError_t e = bh::hilbert_order(t->prec == BH_FP64, (int)t->n, t->w, st);
+    if (e != hipSuccess) return e;
+    t->horder_ready = true;
+  }
+  return hipSuccess;
 }
 
 int run_walk(const bh_tree* t, double theta, const float* theta_group, double eps, void* acc, void* pot,
@@ -198,11 +275,10 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
                                          reinterpret_cast<bh::ThetaNode*>(t->w.wnodes), st);
     if (e != hipSuccess) return hip_fail(e, "launching the per-group walk copy");
   }
-  if (t->target_order == 2 && !t->horder_ready) {
+  {
     // (once per build; a graph that captures the build captures this too)
-    hipError_t e = bh::hilbert_order(t->prec == BH_FP64, (int)t->n, t->w, st);
-    if (e != hipSuccess) return hip_fail(e, "launching the Hilbert target order");
-    t->horder_ready = true;
+    hipError_t e = ensure_target_order(t, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the target order");
   }
   if (t->order == 2 && !t->quad_ready) {
     // (once per build, like the Hilbert order)
@@ -272,7 +348,6 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
 static_assert(BH_NOALLOC_SCRATCH_BYTES % kAlign == 0, "scratch size must keep the workspace alignment");
 static __device__ __align__(256) unsigned char scratch[BH_NOALLOC_SCRATCH_BYTES];
 
-constexpr int kMaxDevices = 64;
 std::mutex g_noalloc_mu;                 // guards the two tables below (host state only)
 void* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
 bh_tree g_noalloc_tree[kMaxDevices];     // host handle of the tree built in `scratch`, per device
@@ -417,7 +492,7 @@ int bh_forces_noalloc(const void* pos, const void* mass, int64_t n, int prec, do
   hipStream_t st = static_cast<hipStream_t>(stream);
   // every array the build and the walk read is written by them first (counters
   // and flags by fill kernels), so the previous call's contents do not matter
-  e = enqueue_build(&t, st);
+  e = enqueue_build(&t, st, false);
   if (e != hipSuccess) return hip_fail(e, "launching the tree build");
   return run_walk(&t, theta, nullptr, eps, acc, pot, bh::kWalkForces, nullptr, nullptr, nullptr, 0, nullptr, st,
                   false);
@@ -510,10 +585,9 @@ int bh_neighbours(const bh_tree* t, double radius, int32_t* count, uint64_t* has
   const size_t el = t->prec == BH_FP64 ? 8 : 4;
   if (rho && !aligned(rho, el)) return fail(BH_EINVAL, "rho must be aligned to %zu bytes", el);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (t->target_order == 2 && !t->horder_ready) {
-    hipError_t e = bh::hilbert_order(t->prec == BH_FP64, (int)t->n, t->w, st);
-    if (e != hipSuccess) return hip_fail(e, "launching the Hilbert target order");
-    t->horder_ready = true;
+  {
+    hipError_t e = ensure_target_order(t, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the target order");
   }
   const int32_t* order = t->target_order == 1 ? t->rank : t->target_order == 2 ? t->w.horder : nullptr;
   const int chunk = t->xcd_chunk >= 0 ? t->xcd_chunk : (t->prec == BH_FP64 ? 0 : 1024);
@@ -530,10 +604,9 @@ int bh_walk_order(const bh_tree* t, int32_t* order, void* stream) {
   if (t->n == 0) return BH_OK;
   if (!order || !aligned(order, 4)) return fail(BH_EINVAL, "order must be a non-null device array of int32");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (t->target_order == 2 && !t->horder_ready) {
-    hipError_t e = bh::hilbert_order(t->prec == BH_FP64, (int)t->n, t->w, st);
-    if (e != hipSuccess) return hip_fail(e, "launching the Hilbert target order");
-    t->horder_ready = true;
+  {
+    hipError_t e = ensure_target_order(t, st);
+    if (e != hipSuccess) return hip_fail(e, "launching the target order");
   }
   const int32_t* pos_order = t->target_order == 1 ? t->rank : t->target_order == 2 ? t->w.horder : nullptr;
   hipError_t e = bh::launch_walk_order(pos_order, t->w.idx_a, (int)t->n, order, st);
@@ -667,9 +740,10 @@ int bh_graph_create(bh_tree* t, double theta, double eps, void* acc, void* pot, 
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     // nothing captured has run: an eager walk before the first replay must
-    // form the Hilbert order and the second moments itself
+    // form the target order and the second moments itself
     t->horder_ready = false;
     t->quad_ready = false;
+    t->rank_ready = false;
     if (eb != hipSuccess) e = eb;
     if (e == hipSuccess && wrc != BH_OK) {
       if (graph) (void)hipGraphDestroy(graph);

@@ -790,9 +790,9 @@ __global__ __launch_bounds__(256) void k_nodes_leaf(const Counts* __restrict__ c
 //  * k_moments_chunk: a workgroup loads a chunk of kChunk consecutive preorder
 //    nodes (next, level, the leaves' moments) into LDS and folds there, level
 //    by level (deepest first), every internal node whose subtree ends inside
-//    the chunk.  The others, at most one per level, are put in their level's
-//    list together with their children (read along next, past the chunk's
-//    end from memory);
+//    the chunk.  The others, at most one per level, go to the chunk's slot of
+//    their level's list, and k_open_kids lists their children (along next,
+//    which past the chunk's end continues in memory);
 //  * k_moments_top: one launch per level folds that level's listed nodes
 //    from their children's records in memory.
 // A node's children are deeper than it, so each fold reads finished values.
@@ -820,16 +820,20 @@ __device__ void chunk_sort(ChunkIndex& ci, int c0, int cn) {
   for (int i = tid; i < cn; i += blockDim.x)
     if (!chunk_leaf(ci, c0, i) && ci.nx[i] <= c1) atomicAdd(&ci.fill[ci.lv[i]], 1);
   __syncthreads();
-  if (tid == 0) {
-    int acc = 0, nl = 0;
-    for (int L = 0; L <= kLevels; ++L) {
-      ci.start[L] = acc;
-      acc += ci.fill[L];
+  if (tid < kWave) {
+    // (one wave: an exclusive scan of the level counts, and the non-empty
+    // levels, deepest first)
+    const int cntL = tid <= kLevels ? ci.fill[tid] : 0;
+    int incl = cntL;
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(incl, o, kWave);
+      if (tid >= o) incl += u;
     }
-    ci.start[kLevels + 1] = acc;
-    for (int L = kLevels; L >= 0; --L)
-      if (ci.fill[L]) ci.levels[nl++] = L;
-    ci.n_levels = nl;
+    if (tid <= kLevels) ci.start[tid] = incl - cntL;
+    if (tid == kLevels) ci.start[kLevels + 1] = incl;
+    const uint64_t ne = __ballot(tid <= kLevels && cntL > 0);
+    if (tid <= kLevels && cntL > 0) ci.levels[__popcll(ne >> (tid + 1))] = tid;
+    if (tid == 0) ci.n_levels = __popcll(ne);
   }
   __syncthreads();
   if (tid <= kLevels) ci.fill[tid] = 0;
@@ -849,10 +853,10 @@ __device__ __forceinline__ void add_mom(Mom& s, const Mom& q) {
   s.Z += q.Z;
 }
 
-// Centre of mass and s of node p from its folded moments q; the node record
-// holds its cube's centre until here.
-__device__ __forceinline__ void finish_node(int p, const Mom& q, Node* __restrict__ nodes, Mom* __restrict__ mom) {
-  const double ctr[3] = {nodes[p].cx, nodes[p].cy, nodes[p].cz};
+// Centre of mass and s of node p from its folded moments q and its cube's
+// centre ctr (which the node record holds until here).
+__device__ __forceinline__ void finish_node(int p, const Mom& q, const double ctr[3], Node* __restrict__ nodes,
+                                            Mom* __restrict__ mom) {
   double com[3];
   if (q.M != 0.0) {
     com[0] = q.X / q.M;
@@ -872,11 +876,12 @@ __device__ __forceinline__ void finish_node(int p, const Mom& q, Node* __restric
   mom[p] = q;
 }
 
-__global__ __launch_bounds__(256) void k_moments_chunk(const Counts* __restrict__ cnt, const int32_t* __restrict__ nx,
-                                                       const uint8_t* __restrict__ nlev, Node* __restrict__ nodes,
-                                                       Mom* __restrict__ mom, int32_t* __restrict__ ocnt,
-                                                       int32_t* __restrict__ obkt, int32_t* __restrict__ okids,
-                                                       int nchunks) {
+__global__ __launch_bounds__(kChunkThreads) void k_moments_chunk(const Counts* __restrict__ cnt,
+                                                                 const int32_t* __restrict__ nx,
+                                                                 const uint8_t* __restrict__ nlev,
+                                                                 Node* __restrict__ nodes, Mom* __restrict__ mom,
+                                                                 int32_t* __restrict__ obkt, int nchunks) {
+  constexpr int kItems = kChunk / kChunkThreads;
   __shared__ ChunkIndex ci;
   __shared__ Mom sm[kChunk];
   const int n_nodes = cnt->n_nodes;
@@ -884,17 +889,37 @@ __global__ __launch_bounds__(256) void k_moments_chunk(const Counts* __restrict_
   if (c0 >= n_nodes) return;
   const int cn = min(kChunk, n_nodes - c0), c1 = c0 + cn;
   const int tid = threadIdx.x;
-  for (int i = tid; i < cn; i += blockDim.x) {
-    const int nxt = nx[c0 + i];
-    ci.nx[i] = nxt;
-    ci.lv[i] = (uint8_t)min((int)nlev[c0 + i], kLevels);
-    if (nxt == c0 + i + 1) sm[i] = mom[c0 + i];  // a leaf
+  int nxt[kItems];
+#pragma unroll
+  for (int t = 0; t < kItems; ++t) {
+    const int i = tid + t * kChunkThreads;
+    nxt[t] = i < cn ? nx[c0 + i] : 0;
   }
+#pragma unroll
+  for (int t = 0; t < kItems; ++t) {
+    const int i = tid + t * kChunkThreads;
+    if (i >= cn) continue;
+    ci.nx[i] = nxt[t];
+    ci.lv[i] = (uint8_t)min((int)nlev[c0 + i], kLevels);
+    if (nxt[t] == c0 + i + 1) sm[i] = mom[c0 + i];  // a leaf
+  }
+  // the cube centres of this thread's closed internal nodes, for the end
+  double ctr[kItems][3];
+#pragma unroll
+  for (int t = 0; t < kItems; ++t) {
+    const int i = tid + t * kChunkThreads;
+    const bool closed = i < cn && nxt[t] != c0 + i + 1 && nxt[t] <= c1;
+    ctr[t][0] = closed ? nodes[c0 + i].cx : 0.0;
+    ctr[t][1] = closed ? nodes[c0 + i].cy : 0.0;
+    ctr[t][2] = closed ? nodes[c0 + i].cz : 0.0;
+  }
+  // this chunk's slot of each level's list of straddling nodes: none yet
+  if (tid < kLevels) obkt[tid * nchunks + blockIdx.x] = -1;
   __syncthreads();
   chunk_sort(ci, c0, cn);
   for (int t = 0; t < ci.n_levels; ++t) {
     const int L = ci.levels[t];
-    for (int j = ci.start[L] + tid; j < ci.start[L + 1]; j += blockDim.x) {
+    for (int j = ci.start[L] + tid; j < ci.start[L + 1]; j += kChunkThreads) {
       const int i = ci.ord[j];
       const int end = ci.nx[i] - c0;
       Mom q{0.0, 0.0, 0.0, 0.0};
@@ -904,34 +929,46 @@ __global__ __launch_bounds__(256) void k_moments_chunk(const Counts* __restrict_
     }
     __syncthreads();
   }
-  for (int i = tid; i < cn; i += blockDim.x) {
-    if (chunk_leaf(ci, c0, i)) continue;
-    if (ci.nx[i] <= c1) {
-      finish_node(c0 + i, sm[i], nodes, mom);
-      continue;
+#pragma unroll
+  for (int t = 0; t < kItems; ++t) {
+    const int i = tid + t * kChunkThreads;
+    if (i >= cn || nxt[t] == c0 + i + 1) continue;
+    if (nxt[t] <= c1) {
+      finish_node(c0 + i, sm[i], ctr[t], nodes, mom);
+    } else {
+      // crosses the chunk's end (an ancestor of the next chunk's first node,
+      // the only one of its level here): list it for its level's pass
+      obkt[min((int)ci.lv[i], kLevels - 1) * nchunks + blockIdx.x] = c0 + i;
     }
-    // crosses the chunk's end: list it with its children (past the end, the
-    // chain of next continues in memory)
-    const int L = ci.lv[i];
-    const int slot = min(atomicAdd(ocnt + L, 1), nchunks - 1) + L * nchunks;
-    obkt[slot] = c0 + i;
-    const int end = min(ci.nx[i], n_nodes);
-    int c = c0 + i + 1, k = 0;
-    for (; k < 8 && c < end; ++k) {
-      okids[8 * slot + k] = c;
-      c = max(c < c1 ? ci.nx[c - c0] : nx[c], c + 1);
-    }
-    for (; k < 8; ++k) okids[8 * slot + k] = -1;
   }
 }
 
-__global__ __launch_bounds__(256) void k_moments_top(const Counts* __restrict__ cnt, const int32_t* __restrict__ ocnt,
-                                                     const int32_t* __restrict__ obkt,
+// Children of the listed straddling nodes, along next (past the chunk's end
+// the chain continues in memory), -1 after the last.
+__global__ __launch_bounds__(256) void k_open_kids(const Counts* __restrict__ cnt, const int32_t* __restrict__ obkt,
+                                                   const int32_t* __restrict__ nx, int nchunks,
+                                                   int32_t* __restrict__ okids) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= (int64_t)kLevels * nchunks) return;
+  const int L = (int)(slot / nchunks), j = (int)(slot - (int64_t)L * nchunks);
+  const int n_nodes = cnt->n_nodes;
+  if ((int64_t)j * kChunk >= n_nodes) return;  // a chunk past the last node
+  const int p = obkt[slot];
+  if (p < 0) return;
+  int k = 0;
+  if (p < n_nodes) {
+    const int end = min(nx[p], n_nodes);
+    for (int c = p + 1; k < 8 && c < end; ++k, c = max(nx[c], c + 1)) okids[8 * slot + k] = c;
+  }
+  for (; k < 8; ++k) okids[8 * slot + k] = -1;
+}
+
+__global__ __launch_bounds__(256) void k_moments_top(const Counts* __restrict__ cnt, const int32_t* __restrict__ obkt,
                                                      const int32_t* __restrict__ okids, int nchunks,
                                                      Node* __restrict__ nodes, Mom* __restrict__ mom, int L) {
   const int n_nodes = cnt->n_nodes;
   {
-    const int m = min(ocnt[L], nchunks);
+    const int m = min((n_nodes + kChunk - 1) / kChunk, nchunks);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
       const int slot = L * nchunks + j;
       const int p = obkt[slot];
@@ -942,7 +979,8 @@ __global__ __launch_bounds__(256) void k_moments_top(const Counts* __restrict__ 
         if (c <= p || c >= n_nodes) break;
         add_mom(q, mom[c]);
       }
-      finish_node(p, q, nodes, mom);
+      const double ctr[3] = {nodes[p].cx, nodes[p].cy, nodes[p].cz};
+      finish_node(p, q, ctr, nodes, mom);
     }
   }
 }
@@ -950,8 +988,12 @@ __global__ __launch_bounds__(256) void k_moments_top(const Counts* __restrict__ 
 // ---------------------------------------------------------------- driver
 static inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t) > 0 ? (int)((n + t - 1) / t) : 1; }
 
+template <typename T4>
+static hipError_t hilbert_impl(int n, const BuildWs& w, hipStream_t st);
+
 template <typename T, typename T4>
-static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& w, hipStream_t st) {
+static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& w, const BuildFork* fork,
+                             hipStream_t st) {
   hipError_t e;
   const int K = w.n_seg;
   k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(w.counts), sizeof(Counts) / 4, 0);
@@ -1005,6 +1047,12 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
   // the sorted data must end in key_a / idx_a
   if (kin != w.key_a) k_copy_kv<<<nblk(n, 256), 256, 0, st>>>(kin, vin, w.key_a, w.idx_a, n);
   k_gather<T, T4><<<nblk(n, 256), 256, 0, st>>>(pos, mass, w.idx_a, seg, n, reinterpret_cast<T4*>(w.ps), scid);
+  if (fork) {
+    if ((e = hipEventRecord(fork->fork, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(fork->side, fork->fork, 0)) != hipSuccess) return e;
+    if ((e = hilbert_impl<T4>(n, w, fork->side)) != hipSuccess) return e;
+    if ((e = hipEventRecord(fork->join, fork->side)) != hipSuccess) return e;
+  }
   // unique (cluster, key) pairs
   k_unique_flags<<<nblk(n, 256), 256, 0, st>>>(w.key_a, scid, n, w.flag);
   if ((e = scan_excl(w.flag, w.uid, n, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
@@ -1028,12 +1076,14 @@ static hipError_t build_impl(const T* pos, const T* mass, int n, const BuildWs& 
   // moments: chunks of the preorder (2n nodes at most), then the straddling
   // internal nodes
   const int nch = (int)n_chunks(n);
-  k_fill_i32<<<1, 64, 0, st>>>(w.ocnt, kLevels, 0);
-  k_moments_chunk<<<nch, 256, 0, st>>>(w.counts, w.nx, w.nlev, w.nodes, w.mom, w.ocnt, w.obkt, w.okids, nch);
+  k_moments_chunk<<<nch, kChunkThreads, 0, st>>>(w.counts, w.nx, w.nlev, w.nodes, w.mom, w.obkt, nch);
+  k_open_kids<<<nblk((int64_t)kLevels * nch, 256), 256, 0, st>>>(w.counts, w.obkt, w.nx, nch, w.okids);
   const int tg = nblk(nch, 256);
   for (int L = kLevels - 1; L >= 0; --L)
-    k_moments_top<<<tg, 256, 0, st>>>(w.counts, w.ocnt, w.obkt, w.okids, nch, w.nodes, w.mom, L);
-  return hipGetLastError();
+    k_moments_top<<<tg, 256, 0, st>>>(w.counts, w.obkt, w.okids, nch, w.nodes, w.mom, L);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (fork) return hipStreamWaitEvent(st, fork->join, 0);
+  return hipSuccess;
 }
 
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
@@ -1138,16 +1188,16 @@ static hipError_t hilbert_impl(int n, const BuildWs& w, hipStream_t st) {
   const int levels = hilbert_levels(K);
   const int passes = (3 * levels + bits_of((unsigned)(K - 1)) + 7) / 8;
   k_hkeys<T4><<<nblk(n, 256), 256, 0, st>>>(reinterpret_cast<const T4*>(w.ps), n, w.cube, K > 1 ? w.scid : nullptr,
-                                            levels, w.key_a, w.horder);
+                                            levels, w.hkey_a, w.horder);
   const int ntiles = (n + kSortTile - 1) / kSortTile;
-  uint64_t *kin = w.key_a, *kout = w.key_b;
-  int32_t *vin = w.horder, *vout = w.idx_b;
+  uint64_t *kin = w.hkey_a, *kout = w.hkey_b;
+  int32_t *vin = w.horder, *vout = w.hidx;
   hipError_t e;
   for (int pass = 0; pass < passes; ++pass) {
-    k_rs_hist<kDigKey><<<ntiles, kSortThreads, 0, st>>>(kin, vin, nullptr, w.seg_off, K, n, 8 * pass, w.hist, ntiles);
-    if ((e = scan_excl(w.hist, w.hist, 256 * ntiles, w.scan_tiles, nullptr, st)) != hipSuccess) return e;
+    k_rs_hist<kDigKey><<<ntiles, kSortThreads, 0, st>>>(kin, vin, nullptr, w.seg_off, K, n, 8 * pass, w.hhist, ntiles);
+    if ((e = scan_excl(w.hhist, w.hhist, 256 * ntiles, w.hscan, nullptr, st)) != hipSuccess) return e;
     k_rs_scatter<kDigKey><<<ntiles, kSortThreads, 0, st>>>(kin, vin, nullptr, w.seg_off, K, kout, vout, n, 8 * pass,
-                                                           w.hist, ntiles);
+                                                           w.hhist, ntiles);
     uint64_t* tk = kin; kin = kout; kout = tk;
     int32_t* tv = vin; vin = vout; vout = tv;
   }
@@ -1230,7 +1280,7 @@ __device__ __forceinline__ void quad_fold(double b[6], const double cb[6], doubl
 // from their particles and folds the chunk's closed nodes in LDS; the
 // straddling nodes and their children are the lists the build made.
 template <typename T4>
-__global__ __launch_bounds__(1024) void k_quad_chunk(const Counts* __restrict__ cnt, const int32_t* __restrict__ nx,
+__global__ __launch_bounds__(kChunkThreads) void k_quad_chunk(const Counts* __restrict__ cnt, const int32_t* __restrict__ nx,
                                                     const uint8_t* __restrict__ nlev, const Node* __restrict__ nodes,
                                                     const T4* __restrict__ ps, QuadRec* __restrict__ qr) {
   __shared__ ChunkIndex ci;
@@ -1261,7 +1311,7 @@ __global__ __launch_bounds__(1024) void k_quad_chunk(const Counts* __restrict__ 
   chunk_sort(ci, c0, cn);
   for (int t = 0; t < ci.n_levels; ++t) {
     const int L = ci.levels[t];
-    for (int j = ci.start[L] + tid; j < ci.start[L + 1]; j += blockDim.x) {
+    for (int j = ci.start[L] + tid; j < ci.start[L + 1]; j += kChunkThreads) {
       const int i = ci.ord[j];
       const int end = ci.nx[i] - c0;
       double b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1276,13 +1326,12 @@ __global__ __launch_bounds__(1024) void k_quad_chunk(const Counts* __restrict__ 
     if (!chunk_leaf(ci, c0, i) && ci.nx[i] <= c1) put_quad(qr, c0 + i, sb[i]);
 }
 
-__global__ __launch_bounds__(256) void k_quad_top(const Counts* __restrict__ cnt, const int32_t* __restrict__ ocnt,
-                                                  const int32_t* __restrict__ obkt, const int32_t* __restrict__ okids,
-                                                  int nchunks, const Node* __restrict__ nodes,
-                                                  QuadRec* __restrict__ qr, int L) {
+__global__ __launch_bounds__(256) void k_quad_top(const Counts* __restrict__ cnt, const int32_t* __restrict__ obkt,
+                                                  const int32_t* __restrict__ okids, int nchunks,
+                                                  const Node* __restrict__ nodes, QuadRec* __restrict__ qr, int L) {
   const int n_nodes = cnt->n_nodes;
   {
-    const int m = min(ocnt[L], nchunks);
+    const int m = min((n_nodes + kChunk - 1) / kChunk, nchunks);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
       const int slot = L * nchunks + j;
       const int p = obkt[slot];
@@ -1306,11 +1355,11 @@ template <typename T4>
 static hipError_t quad_impl(int n, const BuildWs& w, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int nch = (int)n_chunks(n);
-  // (87 KB of LDS: one workgroup per CU, so it brings 16 waves)
-  k_quad_chunk<T4><<<nch, 1024, 0, st>>>(w.counts, w.nx, w.nlev, w.nodes, reinterpret_cast<const T4*>(w.ps), w.qrec);
+  k_quad_chunk<T4><<<nch, kChunkThreads, 0, st>>>(w.counts, w.nx, w.nlev, w.nodes, reinterpret_cast<const T4*>(w.ps),
+                                                  w.qrec);
   const int tg = nblk(nch, 256);
   for (int L = kLevels - 1; L >= 0; --L)
-    k_quad_top<<<tg, 256, 0, st>>>(w.counts, w.ocnt, w.obkt, w.okids, nch, w.nodes, w.qrec, L);
+    k_quad_top<<<tg, 256, 0, st>>>(w.counts, w.obkt, w.okids, nch, w.nodes, w.qrec, L);
   return hipGetLastError();
 }
 
@@ -1318,12 +1367,14 @@ hipError_t quad_moments(bool f64, int n, const BuildWs& w, hipStream_t st) {
   return f64 ? quad_impl<double4>(n, w, st) : quad_impl<float4>(n, w, st);
 }
 
-hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st) {
-  return build_impl<float, float4>(pos, mass, n, w, st);
+hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, const BuildFork* fork,
+                          hipStream_t st) {
+  return build_impl<float, float4>(pos, mass, n, w, fork, st);
 }
 
-hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, hipStream_t st) {
-  return build_impl<double, double4>(pos, mass, n, w, st);
+hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, const BuildFork* fork,
+                          hipStream_t st) {
+  return build_impl<double, double4>(pos, mass, n, w, fork, st);
 }
 
 }  // namespace bh

@@ -30,8 +30,9 @@ struct alignas(32) Mom {
 // consecutive preorder nodes in a workgroup's LDS.  The internal nodes whose
 // subtree crosses the chunk's end are ancestors of the next chunk's first node
 // that start in the chunk, so a chunk has at most one per level: they are kept
-// per level, kLevels x (number of chunks) slots, each with its children.
-constexpr int kChunk = 1024;
+// in kLevels x (number of chunks) slots, each with its children.
+constexpr int kChunk = 512;
+constexpr int kChunkThreads = 256;  // workgroup of the chunk launches: kChunk / kChunkThreads nodes per thread
 inline int64_t n_chunks(int64_t n) { return (2 * (n > 0 ? n : 1) + kChunk - 1) / kChunk; }
 
 struct BuildWs {
@@ -62,22 +63,36 @@ struct BuildWs {
   Mom* mom;                 // [2n] mass and first moments of every node, for the moment passes
   int32_t* nx;              // [2n] next(c) of every node, for the moment passes
   uint8_t* nlev;            // [2n] level of every node, for the moment passes
-  int32_t* ocnt;            // [kLevels] straddling internal nodes per level
-  int32_t* obkt;            // [kLevels][n_chunks] the straddling nodes of each level
+  int32_t* obkt;            // [kLevels][n_chunks] the straddling node of each level and chunk, or -1
   int32_t* okids;           // [kLevels][n_chunks][8] their children in octant order, -1 after the last
   WalkNode* wnodes;         // [2n] walk copy of the nodes for the last uniform theta
   int32_t* horder;          // [n] Morton positions in the Hilbert walk order (filled on demand)
+  uint64_t *hkey_a, *hkey_b;  // [n] sort buffers of the Hilbert order (its own: it may run beside the build)
+  int32_t* hidx;            // [n]
+  int32_t* hhist;           // [256 * ntiles]
+  int32_t* hscan;           // scan scratch
   QuadRec* qrec;            // [2n + 1] second moments of every node (walks of order 2; filled on demand)
 };
 
+// A second stream for a build: the Hilbert walk order, which needs only the
+// sorted particles, is formed there while the build goes on (fork is recorded
+// on the build's stream after the particles are sorted, join on the second
+// stream after the order; the build's stream waits for join before it returns).
+struct BuildFork {
+  hipStream_t side;
+  hipEvent_t fork, join;
+};
+
 hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total, hipStream_t st);
-hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, hipStream_t st);
-hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, hipStream_t st);
+hipError_t build_tree_f32(const float* pos, const float* mass, int n, const BuildWs& w, const BuildFork* fork,
+                          hipStream_t st);
+hipError_t build_tree_f64(const double* pos, const double* mass, int n, const BuildWs& w, const BuildFork* fork,
+                          hipStream_t st);
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // Walk order of the targets (w.horder): Morton positions sorted by cluster and
 // the Hilbert index of their cell a few levels below the cluster's root cube.
-// Uses the sort buffers of the build, so it runs after it; w.key_a, w.key_b
-// and w.idx_b are overwritten.
+// Reads the sorted particles (w.ps, w.scid) and the cubes; its scratch arrays
+// are its own.
 hipError_t hilbert_order(bool f64, int n, const BuildWs& w, hipStream_t st);
 // The targets' walk order as caller indices (order: Morton positions, null =
 // Morton order).
