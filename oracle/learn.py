@@ -4,12 +4,14 @@ Only the test suite may import this module (like the rest of ``oracle/``); the
 GPU library never does.  The paper has no learned component: what follows is
 the definition the GPU path is held to, written plainly in numpy.
 
-* ``features``  -- 8 scale-free descriptors of each Morton group of 64
-  particles (group g = Morton positions [64g, 64g+64) of its tree):
+* ``features``  -- 8 scale-free descriptors of each walk group of 64
+  particles (group g = the Morton positions order[64g, 64g+64) of a walk order,
+  by default the Morton order itself):
     0  log2(h / h_typ): AABB half-width h against the half-width a group of 64
        would have in a uniform cube of the same N, h_typ = L (64/N)^(1/3) / 2
     1  |centre of mass - centre of mass of c| / l_c, c the smallest tree cell
-       holding the whole group, l_c its side
+       holding the whole group (the cell of the range [min, max] of its Morton
+       positions), l_c its side
     2  |centre of mass - centre of mass of a| / l_a, a the ancestor of c three
        levels up (or the root)
     3  mass-weighted RMS radius about the group's centre of mass, over h
@@ -160,11 +162,13 @@ def containing_cell(tree, a, b):
     return path[-1], path[-2] if len(path) > 1 else path[-1]
 
 
-def features(tree, pos, mass):
-    """Features [G, 8] of the Morton groups of ``tree`` built from pos [n,3], mass [n] (float64)."""
+def features(tree, pos, mass, order=None):
+    """Features [G, 8] of the walk groups of ``tree`` built from pos [n,3], mass [n] (float64);
+    order: Morton positions in walk order (None: the Morton order)."""
     n = len(pos)
-    ps = np.asarray(pos, np.float64)[tree.perm]
-    ms = np.asarray(mass, np.float64)[tree.perm]
+    order = np.arange(n) if order is None else np.asarray(order, np.int64)
+    ps = np.asarray(pos, np.float64)[tree.perm][order]
+    ms = np.asarray(mass, np.float64)[tree.perm][order]
     L = tree.L
     Mtot = float(tree.M[0]) if len(tree.M) else 0.0
     rho_mean = max(Mtot, 1e-300) / L ** 3
@@ -181,7 +185,7 @@ def features(tree, pos, mass):
         com = (m[:, None] * p).sum(axis=0) / M if M > 0 else gc
         r2 = ((p - com) ** 2).sum(axis=1)
         rms = np.sqrt(float((m * r2).sum()) / M) if M > 0 else 0.0
-        path = containing_path(tree, a, b)
+        path = containing_path(tree, int(order[a:b].min()), int(order[a:b].max()) + 1)
         c = path[-1]
         par = path[-2] if len(path) > 1 else c
         anc = path[-4] if len(path) > 3 else path[0]
@@ -196,13 +200,15 @@ def features(tree, pos, mass):
     return X
 
 
-def group_rms(acc, acc_ref, perm):
-    """Per Morton group: RMS over its particles of |a - a_ref| / |a_ref| (caller-order inputs).
+def group_rms(acc, acc_ref, perm, order=None):
+    """Per walk group (as in features): RMS over its particles of |a - a_ref| / |a_ref|
+    (caller-order inputs).
 
     The relative error of Eq. (4) is undefined where a_ref = 0: such particles are left out of
     their group's mean, and a group with none left has RMS 0."""
-    acc = np.asarray(acc, np.float64)[perm]
-    ref = np.asarray(acc_ref, np.float64)[perm]
+    sel = np.asarray(perm) if order is None else np.asarray(perm)[np.asarray(order, np.int64)]
+    acc = np.asarray(acc, np.float64)[sel]
+    ref = np.asarray(acc_ref, np.float64)[sel]
     den = np.linalg.norm(ref, axis=1)
     ok = den > 0
     d = np.zeros(len(den))

@@ -232,3 +232,47 @@ def test_allocate_ignores_non_finite_groups():
     R3[4, 2] = np.nan
     k3 = plearn.allocate(R3, C, n_g, 2e-3)
     assert k3[2] != 4 and np.all(k3 >= 0)
+
+
+def test_features_walk_groups_brute_force():
+    """Walk groups of the Hilbert order: members order[64g, 64g+64); the containing cell is the
+    deepest cell whose particle range holds every member (brute force over all cells)."""
+    from oracle import hilbert
+    from paper_1112_4539_amd import inputs
+    pos, mass = inputs.clumpy(3000, 9)
+    T = oracle.Tree(pos, mass)
+    order = hilbert.walk_positions(pos, mass)
+    X = learn.features(T, pos, mass, order)
+    n = len(pos)
+    rho_mean = T.M[0] / T.L ** 3
+    for g in range((n + 63) // 64):
+        mem = order[64 * g: 64 * g + 64]
+        holds = [c for c in range(len(T.M)) if np.all((T.first[c] <= mem) & (mem < T.first[c] + T.count[c]))]
+        c = max(holds, key=lambda k: (T.level[k], k))
+        ps = pos[T.perm[mem]]
+        h = max(np.max(ps.max(0) - ps.min(0)) / 2, T.L * 2.0 ** -22)
+        np.testing.assert_allclose(X[g, 5], np.log10(T.M[c] / T.l[c] ** 3 / rho_mean), rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(X[g, 7], np.log2(T.l[c] / h), rtol=1e-12)
+        w = mass[T.perm[mem]]
+        com = (w[:, None] * ps).sum(0) / w.sum()
+        np.testing.assert_allclose(X[g, 4], np.linalg.norm(com - 0.5 * (ps.max(0) + ps.min(0))) / h, rtol=1e-9,
+                                   atol=1e-12)
+    # the Morton order as the walk order gives the Morton groups
+    np.testing.assert_array_equal(learn.features(T, pos, mass, np.arange(n)), learn.features(T, pos, mass))
+
+
+def test_group_rms_walk_groups():
+    # per-particle relative errors e_i planted exactly; group g = order[64g, 64g+64)
+    n = 300
+    rng = np.random.default_rng(10)
+    ref = rng.normal(size=(n, 3))
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    e = rng.uniform(1e-4, 1e-2, n)
+    acc = ref + (e * np.linalg.norm(ref, axis=1))[:, None] * d
+    perm = rng.permutation(n)
+    order = rng.permutation(n)
+    r = learn.group_rms(acc, ref, perm, order)
+    for g in range((n + 63) // 64):
+        mem = perm[order[64 * g: 64 * g + 64]]
+        np.testing.assert_allclose(r[g], np.sqrt(np.mean(e[mem] ** 2)), rtol=1e-9)
