@@ -399,6 +399,67 @@ def quad_steps(args, bh, inputs, gpos, gmass, ws, acc, pot, eps, n, ref):
             "walk_ms": walk, "forces_per_s": n / (ms * 1e-3), "interactions_per_s": inter / (ms * 1e-3)}
 
 
+def learned_headline(args, bh, gpos, gmass, eps, n, ref, fixed):
+    """The shipped opening-parameter network on the headline field, outside the timed region: the
+    per-group theta of the network times one scale alpha, and one fixed theta, each bisected to the
+    RMS error target on the same sampled targets; interactions and walk time (median of 5 launches)
+    of the learned FP32 walk against the fixed-theta FP32 and FP64 walks."""
+    from paper_1112_4539_amd import learn
+    if not os.path.exists(args.weights):
+        return {"weights": None, "note": f"no weight file at {args.weights}"}
+    net, info = learn.load_net(args.weights)
+    tg, a_ref = ref
+    T = bh.Tree(gpos, gmass)
+    T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share, args.persistent,
+                      args.targets_per_lane)
+    raw = net.infer(T.features(), alpha=1.0, fallback=0.5)
+
+    def rms_l(alpha):
+        a, _ = T.forces(0.5, eps, theta_group=learn.scaled_theta(raw, alpha, 1.0))
+        return learn.rms_error(a, a_ref, tg)
+
+    alpha, err = learn.bisect(rms_l, 0.05, 4.0, learn.TARGET)
+    tgrp = learn.scaled_theta(raw, alpha, 1.0)
+    # the fixed theta bisected to the same target (the headline's theta is the largest on a 0.05
+    # grid, a little below it)
+    thf, ef = learn.bisect(lambda th: learn.rms_error(T.forces(th, eps)[0], a_ref, tg), 0.1, 1.1, learn.TARGET)
+
+    def timed(T, theta, tgrp, reps):
+        T.set_timing(True)
+        ms = []
+        for _ in range(reps):
+            T.forces(theta, eps, theta_group=tgrp)
+            ms.append(T.walk_time_ms())
+        T.set_timing(False)
+        return float(np.median(ms))
+
+    def count(theta, tgrp):
+        st = T.walk_stats(theta, eps, theta_group=tgrp)
+        return int(st["counts"].to(torch.int64).sum().item())
+
+    inter, inter_f = count(0.5, tgrp), count(thf, None)
+    ms_l, ms_f = timed(T, 0.5, tgrp, 5), timed(T, thf, None, 5)
+    del T
+    T64 = bh.Tree(gpos.double(), gmass.double())
+    T64.set_walk_config(target_order=args.target_order)
+    a64, _ = T64.forces(thf, eps)
+    rms64 = learn.rms_error(a64, a_ref, tg)
+    ms64 = timed(T64, thf, None, 3)
+    del T64, a64
+    out = {"weights": os.path.relpath(args.weights, ROOT), "trained_on": info.get("fields"),
+           "alpha": alpha, "theta_mean": float(tgrp.mean()), "rms_rel_force_err": err,
+           "interactions": inter, "walk_ms": ms_l,
+           "interactions_vs_fixed": inter / inter_f, "walk_ms_vs_fixed": ms_l / ms_f,
+           "forces_per_s_walk": n / (ms_l * 1e-3),
+           "fixed_fp32": {"theta": thf, "rms_rel_force_err": ef, "interactions": inter_f, "walk_ms": ms_f},
+           "fixed_fp64": {"theta": thf, "rms_rel_force_err": rms64, "walk_ms": ms64},
+           "walk_ms_vs_fixed_fp64": ms_l / ms64,
+           "headline_theta": {"theta": args.theta, "rms_rel_force_err": fixed["rms"],
+                              "interactions": fixed["interactions"], "walk_ms": fixed["walk_ms"]}}
+    log(f"[bench] learned theta: {json.dumps(out)}")
+    return out
+
+
 def leapfrog_bench(args, bh, inputs):
     """The time loop on the clumpy field N=4,194,304 (FP32, theta --theta, eps 1e-4): kick-drift-kick
     leapfrog steps with a tree rebuild each step, with the state kept in the caller's (random) order
@@ -474,6 +535,10 @@ def main():
     ap.add_argument("--samples", type=int, default=65536, help="targets of the accuracy check")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-theta evaluation")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1112_4539_amd", "weights",
+                                                      "theta_clumpy4m.json"),
+                    help="network for the learned-theta evaluation of the headline field")
     ap.add_argument("--cpu-sample", type=int, default=262144)
     ap.add_argument("--cpu-sample-1t", type=int, default=16384, help="walk sample of the one-thread CPU figure")
     ap.add_argument("--waves-per-block", type=int, default=1)
@@ -598,6 +663,11 @@ def main():
         rms = metrics.rms_rel_err(a[tg], a_ref)
         log(f"[bench] RMS rel force err vs FP64 direct on {args.samples} targets: {rms:.3e}")
 
+    learned = None
+    if rms is not None and not args.no_learned:
+        learned = learned_headline(args, bh, gpos, gmass, eps, n, (tg, a_ref),
+                                   {"interactions": inter, "walk_ms": walk_avg, "rms": rms})
+
     quad = None
     if args.quad_theta > 0:
         quad = quad_steps(args, bh, inputs, gpos, gmass, ws, acc, pot, eps, n, None if rms is None else (tg, a_ref))
@@ -631,6 +701,7 @@ def main():
             "rms_rel_force_err": rms, "accuracy_targets": None if rms is None else args.samples,
             "n_nodes": tstats["n_nodes"],
             "quadrupole": quad,
+            "learned_theta": learned,
             "launch": {"waves_per_block": args.waves_per_block, "xcd_chunk": args.xcd_chunk,
                        "target_order": args.target_order, "lds_share": args.lds_share,
                        "persistent": args.persistent, "targets_per_lane": args.targets_per_lane},

@@ -112,13 +112,41 @@ BH_API int bh_tree_stats(const bh_tree *t, void *stream, int64_t *n_nodes, int64
  * BH_FP64 trees evaluate every term in FP64. */
 BH_API int bh_forces(const bh_tree *t, double theta, double eps, void *acc, void *pot, void *stream);
 
-/* Same walk with one opening parameter per Morton group of 64 particles:
+/* Same walk with one opening parameter per walk group of 64 targets:
  * theta_group [ceil(n/64)] device floats, each in (0, 2/sqrt(3)); group g holds
- * the particles at Morton positions [64g, 64g+64).  A value that is not finite
- * or lies outside that range is replaced by 0.5 on the device, and the next
- * bh_tree_check() reports it (BH_EINVAL) until the next per-group walk. */
+ * the targets at positions [64g, 64g+64) of the walk's target order (see
+ * bh_set_walk_config: the Hilbert order by default; under target_order 0 the
+ * Morton positions [64g, 64g+64)).  A value that is not finite or lies outside
+ * that range is replaced by 0.5 on the device, and the next bh_tree_check()
+ * reports it (BH_EINVAL) until the next per-group walk. */
 BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double eps, void *acc, void *pot,
                     void *stream);
+
+#define BH_MAX_THETA_LEVELS 16
+/* Per-group theta from a table of at most BH_MAX_THETA_LEVELS values: walk
+ * group g walks with theta = level_theta[group_level[g]], exactly as
+ * bh_forces_theta with that theta_group (same lists, same results).
+ * group_level [ceil(n/64)] device uint8; level_theta [n_levels] host floats,
+ * each in (0, 2/sqrt(3)); 1 <= n_levels <= BH_MAX_THETA_LEVELS.  On FP32 trees
+ * of expansion order 1 with one target per lane, each level's opening sizes S
+ * are formed once per call for every node (8 bytes per node and level, in the
+ * workspace), and a wavefront reads its group's level as the uniform-theta
+ * walk reads its S: the step costs what a step of bh_forces costs.  Other
+ * trees walk the levels' values as bh_forces_theta does.  A group_level entry
+ * >= n_levels is replaced by level 0 and reported by the next bh_tree_check()
+ * (BH_EINVAL).  Errors: BH_EINVAL for a null tree, group_level, acc or pot, a
+ * level value or n_levels out of range, or eps not finite and >= 0. */
+BH_API int bh_forces_theta_levels(const bh_tree *t, const uint8_t *group_level, const float *level_theta,
+                                  int n_levels, double eps, void *acc, void *pot, void *stream);
+
+/* Levels of per-group theta values: group_level[g] = the largest k with
+ * level_theta[k] <= theta_group[g] (level_theta strictly increasing host
+ * floats, n_levels in [1, BH_MAX_THETA_LEVELS]; a value below level_theta[0]
+ * or not finite gets 0).  theta_group and group_level are device arrays of
+ * `groups` entries.  With level_theta[0] at most the smallest value, every
+ * group's level is at most its theta (rounded down, never up). */
+BH_API int bh_theta_quantize(const float *theta_group, int64_t groups, const float *level_theta, int n_levels,
+                             uint8_t *group_level, void *stream);
 
 /* For callers that cannot allocate memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): build + forces in one call
@@ -231,6 +259,11 @@ BH_API int bh_walk_stats(const bh_tree *t, double theta, const float *theta_grou
                   void *pot, int32_t *counts, uint64_t *hash, int64_t *lists, int64_t maxlen,
                   int32_t *group_steps, void *stream);
 
+/* bh_walk_stats for a walk with theta levels (bh_forces_theta_levels). */
+BH_API int bh_walk_stats_levels(const bh_tree *t, const uint8_t *group_level, const float *level_theta,
+                                int n_levels, double eps, void *acc, void *pot, int32_t *counts, uint64_t *hash,
+                                int64_t *lists, int64_t maxlen, int32_t *group_steps, void *stream);
+
 /* Copy the tree out for inspection: nodes (device, n_nodes records of 64
  * bytes: double com[3], M, l, s; int32 next, first, count, meta with bit 0 =
  * leaf, bit 1 = leaf of several coincident-key particles, bits 8-15 = level)
@@ -318,8 +351,8 @@ BH_API int bh_autotune(bh_tree *t, double theta, double eps, void *acc, void *po
                        bh_walk_config *best, bh_walk_config *tried, int max_tried, int *n_tried);
 
 /* ---- Learned opening parameter (beyond the paper, whose theta is one constant
- * in Eq. (2)): per Morton group of 64 targets, features -> MLP -> theta, used
- * by bh_forces_theta.  MLP 8 -> 64 -> 64 -> 1 with tanh-form GELU and
+ * in Eq. (2)): per walk group of 64 targets (the groups of bh_forces_theta),
+ * features -> MLP -> theta, used by bh_forces_theta.  MLP 8 -> 64 -> 64 -> 1 with tanh-form GELU and
  * theta = 0.2 + 0.8 sigmoid(z); matrix products in bf16 on the matrix cores
  * with FP32 accumulation.  Parameters: flat FP32 device array of n_param = 4801
  * values, W1 [64][8], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 (row-major);
@@ -327,8 +360,9 @@ BH_API int bh_autotune(bh_tree *t, double theta, double eps, void *acc, void *po
  * bh_mlp_prepare and refreshed by bh_mlp_adam.  norm: FP32 [16] = mu[8],
  * 1/sd[8]; the network sees bf16((x - mu) / sd). */
 
-/* Features of every Morton group g of t (Morton positions [64g, 64g+64); in a
- * forest the group's cluster sets N, L and the total mass M): X [ceil(n/64)][8]
+/* Features of every walk group g of t (the targets at [64g, 64g+64) of its
+ * target order; in a forest the cluster of the group's first Morton position
+ * sets N, L and the total mass M): X [ceil(n/64)][8]
  * device FP32, scale-free, with h the half-width of the group's bounding box,
  * c the smallest cell holding the group and l_c its side:
  *   log2(h / (L (64/N)^(1/3) / 2)),
@@ -342,10 +376,11 @@ BH_API int bh_autotune(bh_tree *t, double theta, double eps, void *acc, void *po
  * Errors: BH_EINVAL for a null tree or X. */
 BH_API int bh_features(const bh_tree *t, float *X, void *stream);
 
-/* Per-group force error against a reference: for every Morton group g of t,
- * rms[g] = RMS over its particles of |acc - acc_ref| / |acc_ref| (acc in the
- * tree's precision, acc_ref FP64, both [n][3] caller order; a zero reference
- * force gives inf/NaN).  If label != NULL: label[g] = max(label[g], theta)
+/* Per-group force error against a reference: for every walk group g of t (as
+ * in bh_features), rms[g] = RMS over its particles of |acc - acc_ref| /
+ * |acc_ref| (acc in the tree's precision, acc_ref FP64, both [n][3] caller
+ * order; particles with a zero reference force are left out, and a group of
+ * only such particles has rms 0).  If label != NULL: label[g] = max(label[g], theta)
  * where rms[g] <= target -- called for ascending theta it leaves the largest
  * theta of the grid that meets the target.  rms may be NULL. */
 BH_API int bh_group_error(const bh_tree *t, const void *acc, const double *acc_ref, double theta, double target,

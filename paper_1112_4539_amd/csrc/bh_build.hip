@@ -499,7 +499,10 @@ template <typename T, typename T4>
 __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ pos, const T* __restrict__ mass,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ seg,
                                                 int n, T4* __restrict__ ps, int32_t* __restrict__ scid) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  // (Morton neighbours often sit close together in the caller's order, e.g.
+  // particles of one cluster: runs of consecutive blocks per XCD keep their
+  // source lines in one L2)
+  const int k = remap_block(blockIdx.x, gridDim.x, 64) * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int64_t j = perm[k];
   if (scid) scid[k] = seg[j];

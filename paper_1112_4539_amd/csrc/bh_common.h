@@ -73,6 +73,25 @@ struct alignas(64) ThetaNode {
 };
 static_assert(sizeof(ThetaNode) == 64, "ThetaNode must be 64 bytes");
 
+// The walk's copy of a node for walks with one theta per walk group taken from
+// a table of levels: everything of WalkNode but S, which each level keeps in
+// an array of its own (S_k[c] = (l/theta_k + s)^2, a leaf 0), so that a wave
+// reads its node's centre, FP32 mass and next in one load and its level's S
+// in a second, as in a walk with one theta.
+struct alignas(64) LevelNode {
+  double cx, cy, cz;
+  float M32;
+  int32_t next;
+  int32_t first;
+  int32_t count;
+  int32_t meta;
+  int32_t pad;
+  double M;
+  double pad2;
+};
+static_assert(sizeof(LevelNode) == 64, "LevelNode must be 64 bytes");
+constexpr int kMaxThetaLevels = 16;
+
 // Second moments of a node for walks of order 2 (quadrupole cell terms):
 // B_ab = sum over the node's particles of m (x_a - com_a)(x_b - com_b), FP64,
 // with T = Bxx + Byy + Bzz kept as T/2 (exact) and -3T/2, the two forms the
@@ -114,5 +133,20 @@ __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u,
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Workgroups are dispatched to the 8 XCDs round-robin.  The logical index of
+// workgroup b of nb gives each XCD runs of `chunk` consecutive indices (whose
+// work shares data in that XCD's L2: tree nodes for neighbouring walk groups,
+// source lines for neighbouring gathers), interleaving the runs across XCDs to
+// keep the load even.  A run is at most a 64th of the grid, so that every XCD
+// takes at least 8 runs and a few heavy runs do not leave the others idle.
+__device__ __forceinline__ int remap_block(int b, int nb, int chunk) {
+  if (chunk <= 0) return b;
+  chunk = min(chunk, max(1, nb >> 6));
+  const int full = (nb / (8 * chunk)) * 8 * chunk;
+  if (b >= full) return b;
+  const int k = b >> 3, x = b & 7;
+  return ((k / chunk) * 8 + x) * chunk + (k % chunk);
+}
 
 }  // namespace bh

@@ -51,7 +51,8 @@ __device__ __forceinline__ float gelu_grad(float x) {
 }
 
 // ---------------------------------------------------------------- features
-// Eight scale-free descriptors of Morton group g (positions [64g, 64g+64)):
+// Eight scale-free descriptors of walk group g (the Morton positions at
+// [64g, 64g+64) of the walk order `order`; null: the positions themselves):
 //   0 log2(h / h_typ), h the AABB half-width, h_typ = L (64/N)^(1/3) / 2
 //   1 |centre of mass - centre of mass of c| / l_c, c the smallest cell
 //     holding the group, l_c its side
@@ -61,17 +62,26 @@ __device__ __forceinline__ float gelu_grad(float x) {
 //   5 log10(density of the smallest cell holding the group / M_tot L^-3)
 //   6 the same for that cell's parent
 //   7 log2(side of that cell / h)
-// N, L, M_tot are those of the group's cluster (the whole set for one tree).
+// N, L, M_tot are those of the cluster of the group's first Morton position
+// (the whole set for one tree).
 template <typename T4>
 __global__ __launch_bounds__(256) void k_features(const Node* __restrict__ nodes, const T4* __restrict__ ps,
                                                   const Cube* __restrict__ cubes, const int32_t* __restrict__ scid,
                                                   const int32_t* __restrict__ croot,
                                                   const int64_t* __restrict__ seg_off, int n_seg, int n,
-                                                  float* __restrict__ X) {
+                                                  const int32_t* __restrict__ order, float* __restrict__ X) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int a = 64 * g;
-  if (a >= n) return;
-  const int b = min(n, a + 64);
+  const int s0 = 64 * g;
+  if (s0 >= n) return;
+  const int s1 = min(n, s0 + 64);
+  auto member = [&](int s) { return order ? min(max(order[s], 0), n - 1) : s; };
+  // the group's Morton range [a, b)
+  int a = n, b = 0;
+  for (int s = s0; s < s1; ++s) {
+    const int q = member(s);
+    a = min(a, q);
+    b = max(b, q + 1);
+  }
   const int k = scid ? min(max(scid[a], 0), n_seg - 1) : 0;
   const double L = cubes[k].L;
   const int64_t nk64 = seg_off[k + 1] - seg_off[k];
@@ -81,8 +91,8 @@ __global__ __launch_bounds__(256) void k_features(const Node* __restrict__ nodes
   const double Mtot = nodes[root].M;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   double M = 0.0, Sx = 0.0, Sy = 0.0, Sz = 0.0;
-  for (int q = a; q < b; ++q) {
-    const T4 p = ps[q];
+  for (int s = s0; s < s1; ++s) {
+    const T4 p = ps[member(s)];
     const double x = (double)p.x, y = (double)p.y, z = (double)p.z, m = (double)p.w;
     lo[0] = fmin(lo[0], x); hi[0] = fmax(hi[0], x);
     lo[1] = fmin(lo[1], y); hi[1] = fmax(hi[1], y);
@@ -98,13 +108,13 @@ __global__ __launch_bounds__(256) void k_features(const Node* __restrict__ nodes
     com[0] = Sx / M; com[1] = Sy / M; com[2] = Sz / M;
   }
   double R2 = 0.0;
-  for (int q = a; q < b; ++q) {
-    const T4 p = ps[q];
+  for (int s = s0; s < s1; ++s) {
+    const T4 p = ps[member(s)];
     const double dx = (double)p.x - com[0], dy = (double)p.y - com[1], dz = (double)p.z - com[2];
     R2 += (double)p.w * (dx * dx + dy * dy + dz * dz);
   }
   const double rms = M > 0.0 ? sqrt(R2 / M) : 0.0;
-  // smallest cell holding [a, b): descend from the cluster's root while a
+  // smallest cell holding the group's Morton range [a, b): descend from the cluster's root while a
   // child holds the whole range (at most 21 levels of at most 8 children)
   // (path[0] = c, path[1] = its parent, ... path[3] = three levels up)
   int path[4] = {root, root, root, root};
@@ -152,37 +162,39 @@ __global__ __launch_bounds__(256) void k_features(const Node* __restrict__ nodes
 }
 
 hipError_t launch_features(bool f64, const Node* nodes, const void* ps, const Cube* cubes, const int32_t* scid,
-                           const int32_t* croot, const int64_t* seg_off, int n_seg, int n, float* X,
-                           hipStream_t st) {
+                           const int32_t* croot, const int64_t* seg_off, int n_seg, int n, const int32_t* order,
+                           float* X, hipStream_t st) {
   const int G = (n + 63) / 64;
   if (G == 0) return hipSuccess;
   if (f64)
     k_features<double4><<<(G + 255) / 256, 256, 0, st>>>(nodes, static_cast<const double4*>(ps), cubes, scid,
-                                                         croot, seg_off, n_seg, n, X);
+                                                         croot, seg_off, n_seg, n, order, X);
   else
     k_features<float4><<<(G + 255) / 256, 256, 0, st>>>(nodes, static_cast<const float4*>(ps), cubes, scid, croot,
-                                                        seg_off, n_seg, n, X);
+                                                        seg_off, n_seg, n, order, X);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- group error
-// RMS over group g's particles of |a - a_ref| / |a_ref|; where it is within
-// `target`, label[g] = max(label[g], theta) (labels start at the grid minimum).
+// RMS over walk group g's particles (as in k_features) of |a - a_ref| / |a_ref|;
+// where it is within `target`, label[g] = max(label[g], theta) (labels start
+// at the grid minimum).
 template <typename R>
 __global__ __launch_bounds__(256) void k_group_error(const R* __restrict__ acc, const double* __restrict__ ref,
-                                                     const int32_t* __restrict__ perm, int n, double theta,
+                                                     const int32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ order, int n, double theta,
                                                      double target, double* __restrict__ rms,
                                                      float* __restrict__ label) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int a = 64 * g;
-  if (a >= n) return;
-  const int b = min(n, a + 64);
+  const int s0 = 64 * g;
+  if (s0 >= n) return;
+  const int s1 = min(n, s0 + 64);
   // (a particle whose reference force is exactly zero has no relative error:
   // it is left out, and a group of only such particles has RMS 0)
   double s = 0.0;
   int m = 0;
-  for (int q = a; q < b; ++q) {
-    const int64_t o = perm[q];
+  for (int j = s0; j < s1; ++j) {
+    const int64_t o = perm[order ? min(max(order[j], 0), n - 1) : j];
     const double rx = ref[3 * o], ry = ref[3 * o + 1], rz = ref[3 * o + 2];
     const double dx = (double)acc[3 * o] - rx, dy = (double)acc[3 * o + 1] - ry, dz = (double)acc[3 * o + 2] - rz;
     const double r2 = rx * rx + ry * ry + rz * rz;
@@ -196,16 +208,17 @@ __global__ __launch_bounds__(256) void k_group_error(const R* __restrict__ acc, 
   if (label && r <= target) label[g] = fmaxf(label[g], (float)theta);
 }
 
-hipError_t launch_group_error(bool f64, const void* acc, const double* ref, const int32_t* perm, int n,
-                              double theta, double target, double* rms, float* label, hipStream_t st) {
+hipError_t launch_group_error(bool f64, const void* acc, const double* ref, const int32_t* perm,
+                              const int32_t* order, int n, double theta, double target, double* rms, float* label,
+                              hipStream_t st) {
   const int G = (n + 63) / 64;
   if (G == 0) return hipSuccess;
   if (f64)
-    k_group_error<double><<<(G + 255) / 256, 256, 0, st>>>(static_cast<const double*>(acc), ref, perm, n, theta,
-                                                           target, rms, label);
+    k_group_error<double><<<(G + 255) / 256, 256, 0, st>>>(static_cast<const double*>(acc), ref, perm, order, n,
+                                                           theta, target, rms, label);
   else
-    k_group_error<float><<<(G + 255) / 256, 256, 0, st>>>(static_cast<const float*>(acc), ref, perm, n, theta,
-                                                          target, rms, label);
+    k_group_error<float><<<(G + 255) / 256, 256, 0, st>>>(static_cast<const float*>(acc), ref, perm, order, n,
+                                                          theta, target, rms, label);
   return hipGetLastError();
 }
 

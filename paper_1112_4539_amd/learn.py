@@ -7,10 +7,14 @@ is limited to the label allocation below (an argmin over the theta grid with
 a bisected multiplier), the feature normalisation constants (eight means and
 standard deviations of the training features) and the minibatch shuffles.
 
+Groups: a theta belongs to a walk group, the 64 targets a wavefront walks
+together (runs of 64 of the tree's target order, by default the Hilbert
+order), so that one wavefront walks with one theta.
+
 Labels: a training snapshot is walked at every theta of the grid 0.20, 0.25,
-..., 1.00; for every Morton group g of 64 targets this gives its RMS relative
-force error R[k, g] against the FP64 direct sum and its cost C[k, g] (nodes its
-wavefront visits).  The label is the cost-optimal allocation for the snapshot:
+..., 1.00; for every walk group g this gives its RMS relative force error
+R[k, g] against the FP64 direct sum and its cost C[k, g] (nodes its wavefront
+visits).  The label is the cost-optimal allocation for the snapshot:
 theta*_g = grid[argmin_k C[k, g] + lambda n_g R[k, g]^2], with the multiplier
 lambda bisected so that the snapshot's overall RMS error is the target (1e-3)
 -- the least total cost at that error that per-group choices on the grid can
@@ -26,7 +30,9 @@ global error target); a non-finite output falls back to a fixed theta.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 
 import numpy as np
 import torch
@@ -37,6 +43,9 @@ from paper_1112_4539_amd import inputs, metrics
 THETA_GRID = tuple(round(0.20 + 0.05 * k, 2) for k in range(17))
 TARGET = 1e-3
 N_PARAM = 4801
+WEIGHTS_FORMAT = "theta-mlp-8-64-64-1"
+# the network shipped with the package (written by train_theta.py)
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "theta_clumpy4m.json")
 
 
 def init_params(seed):
@@ -95,8 +104,6 @@ def label_snapshot(pos, mass, eps, grid=THETA_GRID, target=TARGET):
     per-group error and cost tables R, C [len(grid), G]."""
     gp, gm = _dev(pos, torch.float32), _dev(mass, torch.float32)
     T = bh.Tree(gp, gm)
-    # costs per Morton group, the groups a per-group theta belongs to
-    T.set_walk_config(target_order=0)
     X = T.features()
     # the reference sees exactly the FP32 values the walk sees
     a_ref, _ = bh.direct(gp.double(), gm.double(), eps)
@@ -115,20 +122,19 @@ def label_snapshot(pos, mass, eps, grid=THETA_GRID, target=TARGET):
 
 
 def label_sampled(pos, mass, eps, n_groups, seed, grid=THETA_GRID, target=TARGET):
-    """Features [S, 8] and labels [S] (device float32) of S = n_groups Morton groups sampled
+    """Features [S, 8] and labels [S] (device float32) of S = n_groups walk groups sampled
     (without replacement, from default_rng(seed); the last, possibly ragged group excluded) from one
     particle set, plus their error and cost tables R, C [len(grid), S].  Labels as in
     label_snapshot, the allocation taken over the sample: for large sets the direct sum then covers
     only the sampled groups' 64 S targets."""
     gp, gm = _dev(pos, torch.float32), _dev(mass, torch.float32)
     T = bh.Tree(gp, gm)
-    T.set_walk_config(target_order=0)  # costs per Morton group, as in label_snapshot
     X = T.features()
     n, G = T.n, T.n_groups
     n_groups = min(n_groups, G - 1)
     gs = np.sort(np.random.default_rng(seed).choice(G - 1, n_groups, replace=False))
-    _, perm = T.export()
-    targets = np.asarray(perm, np.int64)[(gs[:, None] * 64 + np.arange(64)[None, :]).ravel()]
+    order = T.walk_order().cpu().numpy().astype(np.int64)  # caller indices in walk order
+    targets = order[(gs[:, None] * 64 + np.arange(64)[None, :]).ravel()]
     tg = torch.tensor(targets, device="cuda")
     a_s, _ = bh.direct(gp.double(), gm.double(), eps, tg)
     a_ref = torch.zeros((n, 3), dtype=torch.float64, device="cuda")  # groups outside the sample: unused
@@ -214,6 +220,27 @@ def train(X, labels, epochs=40, batch=4096, lr=3e-3, lr_end=3e-4, seed=0, log=No
         if log and (ep % 10 == 0 or ep == epochs - 1):
             log(f"[learn] epoch {ep} loss {history[-1]:.5f}")
     return net, history
+
+
+def save_net(path, net, info):
+    """Writes the network's FP32 parameters and normalisation (exactly: every FP32 value is a JSON
+    number that converts back to itself) with a description of its training."""
+    rec = {"format": WEIGHTS_FORMAT, "n_param": int(net.params.numel()),
+           "params": [float(x) for x in net.params.cpu().numpy()],
+           "norm": [float(x) for x in net.norm.cpu().numpy()], "info": info}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(rec, f)
+    os.replace(tmp, path)
+
+
+def load_net(path=DEFAULT_WEIGHTS, device="cuda"):
+    """(MLP, info) from a file written by save_net."""
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("format") != WEIGHTS_FORMAT or len(rec["params"]) != N_PARAM or len(rec["norm"]) != 16:
+        raise ValueError(f"{path}: not a {WEIGHTS_FORMAT} weight file")
+    return bh.MLP(np.asarray(rec["params"], np.float32), np.asarray(rec["norm"], np.float32), device), rec["info"]
 
 
 def scaled_theta(raw, alpha, beta, cap=1.15):

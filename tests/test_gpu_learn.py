@@ -32,9 +32,16 @@ def bh():
     return bh
 
 
-@pytest.mark.parametrize("which,prec", [("plummer", "fp64"), ("plummer", "fp32"), ("clumpy", "fp32")])
-def test_features_match_oracle(bh, which, prec):
-    say(f"[learn] features {which} {prec}")
+def _oracle_order(p64, m64, target_order):
+    """Morton positions in walk order from the oracle's own construction (None: Morton order)."""
+    from oracle import hilbert
+    return hilbert.walk_positions(p64, m64) if target_order == 2 else None
+
+
+@pytest.mark.parametrize("which,prec,order", [("plummer", "fp64", 2), ("plummer", "fp32", 2), ("clumpy", "fp32", 2),
+                                              ("clumpy", "fp32", 0), ("plummer", "fp64", 0)])
+def test_features_match_oracle(bh, which, prec, order):
+    say(f"[learn] features {which} {prec}, walk groups of target order {order}")
     if which == "plummer":
         pos, mass = inputs.plummer(20_011, 31)
         mass = mass * np.random.default_rng(3).uniform(0.5, 1.5, len(mass))
@@ -43,28 +50,32 @@ def test_features_match_oracle(bh, which, prec):
     dt = torch.float32 if prec == "fp32" else torch.float64
     npdt = np.float32 if prec == "fp32" else np.float64
     T = bh.Tree(torch.tensor(pos, dtype=dt, device="cuda"), torch.tensor(mass, dtype=dt, device="cuda"))
+    T.set_walk_config(target_order=order)
     X = T.features().cpu().numpy().astype(np.float64)
     p64, m64 = pos.astype(npdt).astype(np.float64), mass.astype(npdt).astype(np.float64)
-    Xo = olearn.features(oracle.Tree(p64, m64), p64, m64)
+    Xo = olearn.features(oracle.Tree(p64, m64), p64, m64, _oracle_order(p64, m64, order))
     assert X.shape == Xo.shape
     np.testing.assert_allclose(X, Xo, rtol=2e-6, atol=2e-6)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_group_error_and_labels(bh, prec):
-    say(f"[learn] group error {prec}")
+@pytest.mark.parametrize("prec,order", [("fp32", 2), ("fp64", 2), ("fp32", 0)])
+def test_group_error_and_labels(bh, prec, order):
+    say(f"[learn] group error {prec}, walk groups of target order {order}")
     pos, mass = inputs.plummer(9_000, 35)
     dt = torch.float32 if prec == "fp32" else torch.float64
     T = bh.Tree(torch.tensor(pos, dtype=dt, device="cuda"), torch.tensor(mass, dtype=dt, device="cuda"))
+    T.set_walk_config(target_order=order)
     rng = np.random.default_rng(5)
     ref = rng.normal(size=(len(pos), 3))
     acc = ref * (1 + rng.normal(0, 1e-3, (len(pos), 1)))
     label = torch.full((T.n_groups,), 0.2, dtype=torch.float32, device="cuda")
     rms = T.group_error(torch.tensor(acc, dtype=dt, device="cuda"), torch.tensor(ref, device="cuda"), 0.45, 1e-3,
                         label)
-    _, perm = T.export()
     acc_seen = acc.astype(np.float32 if prec == "fp32" else np.float64)
-    want = olearn.group_rms(acc_seen, ref, perm)
+    npdt = np.float32 if prec == "fp32" else np.float64
+    p64, m64 = pos.astype(npdt).astype(np.float64), mass.astype(npdt).astype(np.float64)
+    # (the oracle's own tree gives the Morton order and the walk groups)
+    want = olearn.group_rms(acc_seen, ref, oracle.Tree(p64, m64).perm, _oracle_order(p64, m64, order))
     np.testing.assert_allclose(rms.cpu().numpy(), want, rtol=1e-12)
     np.testing.assert_array_equal(label.cpu().numpy(), np.where(want <= 1e-3, np.float32(0.45), np.float32(0.2)))
 
@@ -116,6 +127,32 @@ def test_mlp_gradient_matches_oracle(bh, batch):
         err = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
         say(f"  {name}: rel err {err:.2e}")
         assert err <= 1e-3, name
+
+
+def test_shipped_network_round_trip_and_oracle(bh, tmp_path):
+    """The shipped weight file loads into the MLP kernels, its network's theta on the features of a
+    clumpy field agrees with the oracle's forward pass, and save/load keeps every parameter."""
+    say("[learn] shipped network")
+    from paper_1112_4539_amd import learn
+    net, info = learn.load_net()
+    pos, mass = inputs.clumpy(65_536, 41)
+    T = bh.Tree(torch.tensor(pos.astype(np.float32), device="cuda"),
+                torch.tensor(mass.astype(np.float32), device="cuda"))
+    X = T.features()
+    th = net.infer(X).cpu().numpy().astype(np.float64)
+    P = net.params.cpu().numpy().astype(np.float64)
+    norm = net.norm.cpu().numpy().astype(np.float64)
+    f = olearn.forward(P, X.cpu().numpy().astype(np.float64), norm[:8], norm[8:])
+    d = np.abs(th - f["theta"])
+    say(f"  {info['fields']}: theta mean {th.mean():.3f}, max |dtheta| vs oracle {d.max():.2e}")
+    assert np.all(np.isfinite(th)) and np.all((th > 0.0) & (th <= 1.15))
+    assert d.max() <= 1e-3 and np.median(d) <= 1e-5
+    path = str(tmp_path / "net.json")
+    learn.save_net(path, net, info)
+    net2, info2 = learn.load_net(path)
+    assert info2 == info
+    assert torch.equal(net2.params, net.params) and torch.equal(net2.norm, net.norm)
+    assert torch.equal(net2.infer(X), net.infer(X))
 
 
 def test_adam_matches_oracle(bh):

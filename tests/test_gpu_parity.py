@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_1112_4539_amd import inputs
-from tests.util import check_forces, force_err, pot_err, tree_cases, widen
+from tests.util import walk_slots, check_forces, force_err, pot_err, tree_cases, widen
 
 pytestmark = pytest.mark.gpu
 
@@ -88,10 +88,11 @@ def test_tree_bitexact_workloads(bh, which, prec):
     _compare_trees(bh, pos, mass, prec)
 
 
-def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta_group=None, tpl=1):
+def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta_group=None, tpl=1,
+                  target_order=2):
     gp, gm = _gpu(pos, mass, prec)
     T = bh.Tree(gp, gm)
-    T.set_walk_config(targets_per_lane=tpl)
+    T.set_walk_config(targets_per_lane=tpl, target_order=target_order)
     tg_t = None if theta_group is None else torch.tensor(theta_group, dtype=torch.float32, device="cuda")
     out = T.walk_stats(theta, eps, theta_group=tg_t, maxlen=maxlen)
     acc_f, pot_f = T.forces(theta, eps, theta_group=tg_t)
@@ -103,9 +104,13 @@ def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta
     idx = np.arange(len(pos)) if targets is None else targets
     tpt = None
     if theta_group is not None:
-        rank = np.empty(len(pos), np.int64)
-        rank[O.perm] = np.arange(len(pos))
-        tpt = np.asarray(theta_group, np.float32).astype(np.float64)[rank[idx] // 64]
+        # theta of the target's walk group (runs of 64 of the Hilbert order, or of the Morton order)
+        if target_order == 2:
+            slots = walk_slots(p64, m64)
+        else:
+            slots = np.empty(len(pos), np.int64)
+            slots[O.perm] = np.arange(len(pos))
+        tpt = np.asarray(theta_group, np.float32).astype(np.float64)[slots[idx] // 64]
     w = O.walk(theta, eps, targets=idx, theta_per_target=tpt, maxlen=maxlen)
     cnt = out["counts"].cpu().numpy()[idx]
     np.testing.assert_array_equal(cnt[:, 0], w["n_pp"])
@@ -150,15 +155,17 @@ def test_lists_theta_above_one(bh, prec, theta):
     assert pot_err(pot, w["pot"]).max() <= tol
 
 
-@pytest.mark.parametrize("prec,tpl", [("fp32", 1), ("fp32", 2), ("fp64", 1)])
-def test_theta_per_group(bh, prec, tpl):
-    """Per-group theta in [0.2, 1.15]: the FP32 walk reads its own node copy (l, s), the FP64 walk
-    the plain nodes; lists must equal the oracle's per-target-theta walk in both."""
-    say(f"[walk] per-group theta, clumpy 50k {prec}, {tpl} targets per lane")
+@pytest.mark.parametrize("prec,tpl,order", [("fp32", 1, 2), ("fp32", 2, 2), ("fp64", 1, 2), ("fp32", 1, 0),
+                                            ("fp64", 1, 0)])
+def test_theta_per_group(bh, prec, tpl, order):
+    """Per-group theta in [0.2, 1.15], one value per walk group (runs of 64 of the Hilbert order,
+    or of the Morton order): the FP32 walk reads its own node copy (l, s), the FP64 walk the plain
+    nodes; lists must equal the oracle's per-target-theta walk in both."""
+    say(f"[walk] per-group theta, clumpy 50k {prec}, {tpl} targets per lane, target order {order}")
     pos, mass = inputs.clumpy(50_000, 31)
     g = (len(pos) + 63) // 64
     tg = np.random.default_rng(3).uniform(0.2, 1.15, g).astype(np.float32)
-    acc, pot, w = _walk_compare(bh, pos, mass, prec, 0.5, 1e-4, theta_group=tg, tpl=tpl)
+    acc, pot, w = _walk_compare(bh, pos, mass, prec, 0.5, 1e-4, theta_group=tg, tpl=tpl, target_order=order)
     tol = F32_TOL if prec == "fp32" else F64_TOL
     check_forces(acc, w["acc"], w["amag"], tol, prec, log=say)
     assert pot_err(pot, w["pot"]).max() <= tol
@@ -329,9 +336,7 @@ def test_theta_per_group_invalid_values(bh):
         fixed[k] = 0.5
     p64, m64 = _seen(pos, mass, "fp32")
     O = oracle.Tree(p64, m64)
-    rank = np.empty(len(pos), np.int64)
-    rank[O.perm] = np.arange(len(pos))
-    w = O.walk(0.5, 1e-4, theta_per_target=fixed.astype(np.float64)[rank // 64])
+    w = O.walk(0.5, 1e-4, theta_per_target=fixed.astype(np.float64)[walk_slots(p64, m64) // 64])
     np.testing.assert_array_equal(out["hash"].cpu().numpy().view(np.uint64), w["hash"])
     check_forces(out["acc"].cpu().numpy(), w["acc"], w["amag"], F32_TOL, "fallback", log=say)
     T.forces(0.5, 1e-4, theta_group=torch.tensor(fixed, device="cuda"))
@@ -388,3 +393,41 @@ def test_hilbert_walk_order_on_a_lattice(bh, b, prec):
             assert np.all(steps == 1), (order, np.unique(steps))
         else:
             assert steps.max() > 1
+
+
+@pytest.mark.parametrize("case,prec", [("clumpy", "fp32"), ("duplicates", "fp32"), ("plummer", "fp64"),
+                                       ("forest", "fp32")])
+def test_hilbert_walk_order_matches_oracle(bh, case, prec):
+    """The Hilbert target order (Sec. 5's Peano-Hilbert remark) element by element against the
+    oracle's (oracle/hilbert.py: Skilling's transform of the cell ten levels below the root cube,
+    ties in Morton order; per cluster with fewer levels in a forest)."""
+    from oracle import hilbert
+    say(f"[hilbert] walk order vs oracle: {case} {prec}")
+    offsets = None
+    if case == "clumpy":
+        pos, mass = inputs.clumpy(150_001, 12)
+    elif case == "duplicates":
+        pos, mass = inputs.clumpy(60_000, 13)
+        pos[40_000:] = pos[:20_000]          # coincident pairs: ties of the key
+    elif case == "plummer":
+        pos, mass = inputs.plummer(70_000, 14)
+    else:
+        rng = np.random.default_rng(15)
+        sizes = rng.integers(1, 3000, 40)
+        sizes[3] = 1
+        offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        pos = rng.random((offsets[-1], 3)) + np.repeat(rng.random((40, 3)) * 10, sizes, axis=0)
+        mass = rng.uniform(0.5, 1.5, offsets[-1])
+    gp, gm = _gpu(pos, mass, prec)
+    if offsets is None:
+        T = bh.Tree(gp, gm)
+    else:
+        T = bh.build_forest(gp, gm, torch.tensor(offsets, device="cuda"))
+    T.set_walk_config(target_order=2)
+    got = T.walk_order().cpu().numpy().astype(np.int64)
+    # the oracle sees exactly the values the GPU tree is built from
+    p64 = gp.double().cpu().numpy()
+    want = hilbert.walk_order(p64, gm.double().cpu().numpy(), offsets)
+    bad = np.flatnonzero(got != want)
+    say(f"  n={len(pos)} mismatches={len(bad)}")
+    assert len(bad) == 0, bad[:10]

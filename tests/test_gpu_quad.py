@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_1112_4539_amd import inputs
-from tests.util import check_forces, pot_err, tree_cases
+from tests.util import walk_slots, check_forces, pot_err, tree_cases
 
 pytestmark = pytest.mark.gpu
 
@@ -80,9 +80,8 @@ def _walk_compare(bh, pos, mass, prec, theta, eps, targets=None, maxlen=0, theta
     idx = np.arange(len(pos)) if targets is None else targets
     tpt = None
     if theta_group is not None:
-        rank = np.empty(len(pos), np.int64)
-        rank[O.perm] = np.arange(len(pos))
-        tpt = np.asarray(theta_group, np.float32).astype(np.float64)[rank[idx] // 64]
+        # theta of the target's walk group (the Hilbert order's runs of 64)
+        tpt = np.asarray(theta_group, np.float32).astype(np.float64)[walk_slots(p64, m64)[idx] // 64]
     w = O.walk(theta, eps, targets=idx, theta_per_target=tpt, maxlen=maxlen, order=2)
     cnt = out["counts"].cpu().numpy()[idx]
     np.testing.assert_array_equal(cnt[:, 0], w["n_pp"])

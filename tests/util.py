@@ -48,6 +48,16 @@ def check_forces(acc, acc_ref, amag, tol, label="", max_floor_share=1e-3, log=pr
     return e
 
 
+def walk_slots(pos64, mass64):
+    """Position of every target (caller index) in the walk's default target order (the Hilbert
+    order, from the oracle's own construction): target i belongs to walk group slots[i] // 64."""
+    from oracle import hilbert
+    order = hilbert.walk_order(pos64, mass64)
+    slots = np.empty(len(order), np.int64)
+    slots[order] = np.arange(len(order))
+    return slots
+
+
 def pot_err(pot, pot_ref):
     """Relative potential error (absolute where the reference is exactly 0)."""
     pot = widen(pot)
