@@ -414,40 +414,41 @@ def learned_headline(args, bh, gpos, gmass, eps, n, ref, fixed):
                       args.targets_per_lane)
     raw = net.infer(T.features(), alpha=1.0, fallback=0.5)
 
-    def rms_l(alpha):
-        a, _ = T.forces(0.5, eps, theta_group=learn.scaled_theta(raw, alpha, 1.0))
-        return learn.rms_error(a, a_ref, tg)
+    def per_group(alpha):
+        return {"theta_group": learn.scaled_theta(raw, alpha, 1.0)}
 
-    alpha, err = learn.bisect(rms_l, 0.05, 4.0, learn.TARGET)
-    tgrp = learn.scaled_theta(raw, alpha, 1.0)
-    # the fixed theta bisected to the same target (the headline's theta is the largest on a 0.05
-    # grid, a little below it)
-    thf, ef = learn.bisect(lambda th: learn.rms_error(T.forces(th, eps)[0], a_ref, tg), 0.1, 1.1, learn.TARGET)
+    def rms(kw):
+        return learn.rms_error(T.forces(0.5, eps, **kw)[0], a_ref, tg)
 
-    def timed(T, theta, tgrp, reps):
+    def timed(T, reps, theta=0.5, **kw):
         T.set_timing(True)
         ms = []
         for _ in range(reps):
-            T.forces(theta, eps, theta_group=tgrp)
+            T.forces(theta, eps, **kw)
             ms.append(T.walk_time_ms())
         T.set_timing(False)
         return float(np.median(ms))
 
-    def count(theta, tgrp):
-        st = T.walk_stats(theta, eps, theta_group=tgrp)
+    def count(theta=0.5, **kw):
+        st = T.walk_stats(theta, eps, **kw)
         return int(st["counts"].to(torch.int64).sum().item())
 
-    inter, inter_f = count(0.5, tgrp), count(thf, None)
-    ms_l, ms_f = timed(T, 0.5, tgrp, 5), timed(T, thf, None, 5)
+    alpha, err = learn.bisect(lambda a: rms(per_group(a)), 0.05, 4.0, learn.TARGET)
+    kw_g = per_group(alpha)
+    # the fixed theta bisected to the same target (the headline's theta is the largest on a 0.05
+    # grid, a little below it)
+    thf, ef = learn.bisect(lambda th: learn.rms_error(T.forces(th, eps)[0], a_ref, tg), 0.1, 1.1, learn.TARGET)
+    inter, inter_f = count(**kw_g), count(thf)
+    ms_l, ms_f = timed(T, 5, **kw_g), timed(T, 5, thf)
     del T
     T64 = bh.Tree(gpos.double(), gmass.double())
     T64.set_walk_config(target_order=args.target_order)
     a64, _ = T64.forces(thf, eps)
     rms64 = learn.rms_error(a64, a_ref, tg)
-    ms64 = timed(T64, thf, None, 3)
+    ms64 = timed(T64, 3, thf)
     del T64, a64
     out = {"weights": os.path.relpath(args.weights, ROOT), "trained_on": info.get("fields"),
-           "alpha": alpha, "theta_mean": float(tgrp.mean()), "rms_rel_force_err": err,
+           "alpha": alpha, "theta_mean": float(kw_g["theta_group"].mean()), "rms_rel_force_err": err,
            "interactions": inter, "walk_ms": ms_l,
            "interactions_vs_fixed": inter / inter_f, "walk_ms_vs_fixed": ms_l / ms_f,
            "forces_per_s_walk": n / (ms_l * 1e-3),

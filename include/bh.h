@@ -122,32 +122,6 @@ BH_API int bh_forces(const bh_tree *t, double theta, double eps, void *acc, void
 BH_API int bh_forces_theta(const bh_tree *t, const float *theta_group, double eps, void *acc, void *pot,
                     void *stream);
 
-#define BH_MAX_THETA_LEVELS 16
-/* Per-group theta from a table of at most BH_MAX_THETA_LEVELS values: walk
- * group g walks with theta = level_theta[group_level[g]], exactly as
- * bh_forces_theta with that theta_group (same lists, same results).
- * group_level [ceil(n/64)] device uint8; level_theta [n_levels] host floats,
- * each in (0, 2/sqrt(3)); 1 <= n_levels <= BH_MAX_THETA_LEVELS.  On FP32 trees
- * of expansion order 1 with one target per lane, each level's opening sizes S
- * are formed once per call for every node (8 bytes per node and level, in the
- * workspace), and a wavefront reads its group's level as the uniform-theta
- * walk reads its S: the step costs what a step of bh_forces costs.  Other
- * trees walk the levels' values as bh_forces_theta does.  A group_level entry
- * >= n_levels is replaced by level 0 and reported by the next bh_tree_check()
- * (BH_EINVAL).  Errors: BH_EINVAL for a null tree, group_level, acc or pot, a
- * level value or n_levels out of range, or eps not finite and >= 0. */
-BH_API int bh_forces_theta_levels(const bh_tree *t, const uint8_t *group_level, const float *level_theta,
-                                  int n_levels, double eps, void *acc, void *pot, void *stream);
-
-/* Levels of per-group theta values: group_level[g] = the largest k with
- * level_theta[k] <= theta_group[g] (level_theta strictly increasing host
- * floats, n_levels in [1, BH_MAX_THETA_LEVELS]; a value below level_theta[0]
- * or not finite gets 0).  theta_group and group_level are device arrays of
- * `groups` entries.  With level_theta[0] at most the smallest value, every
- * group's level is at most its theta (rounded down, never up). */
-BH_API int bh_theta_quantize(const float *theta_group, int64_t groups, const float *level_theta, int n_levels,
-                             uint8_t *group_level, void *stream);
-
 /* For callers that cannot allocate memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): build + forces in one call
  * for up to BH_NOALLOC_MAX_N particles, with no workspace argument.  Every
@@ -258,11 +232,6 @@ BH_API int bh_tree_moments2(const bh_tree *t, double *B, void *stream);
 BH_API int bh_walk_stats(const bh_tree *t, double theta, const float *theta_group, double eps, void *acc,
                   void *pot, int32_t *counts, uint64_t *hash, int64_t *lists, int64_t maxlen,
                   int32_t *group_steps, void *stream);
-
-/* bh_walk_stats for a walk with theta levels (bh_forces_theta_levels). */
-BH_API int bh_walk_stats_levels(const bh_tree *t, const uint8_t *group_level, const float *level_theta,
-                                int n_levels, double eps, void *acc, void *pot, int32_t *counts, uint64_t *hash,
-                                int64_t *lists, int64_t maxlen, int32_t *group_steps, void *stream);
 
 /* Copy the tree out for inspection: nodes (device, n_nodes records of 64
  * bytes: double com[3], M, l, s; int32 next, first, count, meta with bit 0 =

@@ -63,9 +63,6 @@ def load():
         "bh_tree_stats": ([P, P, P, P, P], i32),
         "bh_forces": ([P, d, d, P, P, P], i32),
         "bh_forces_theta": ([P, P, d, P, P, P], i32),
-        "bh_forces_theta_levels": ([P, P, P, i32, d, P, P, P], i32),
-        "bh_walk_stats_levels": ([P, P, P, i32, d, P, P, P, P, P, i64, P, P], i32),
-        "bh_theta_quantize": ([P, i64, P, i32, P, P], i32),
         "bh_forces_noalloc": ([P, P, i64, i32, d, d, P, P, P], i32),
         "bh_walk_stats": ([P, d, P, d, P, P, P, P, P, i64, P, P], i32),
         "bh_tree_export": ([P, P, P, P], i32),
@@ -317,25 +314,10 @@ class Tree:
             raise ValueError(f"theta_group must be a float32 device tensor of shape [{g}]")
         return theta_group.contiguous()
 
-    def _theta_levels(self, theta_levels):
-        """(group_level uint8 device [groups], level_theta host floats) -> ctypes arguments."""
-        gl, lt = theta_levels
-        g = (self.n + 63) // 64
-        if gl.shape != (g,) or gl.dtype != torch.uint8 or gl.device != self.device:
-            raise ValueError(f"group_level must be a uint8 device tensor of shape [{g}]")
-        arr = (ctypes.c_float * len(lt))(*[float(x) for x in lt])
-        return gl.contiguous(), arr, len(lt)
-
-    def forces(self, theta=0.5, eps=0.0, acc=None, pot=None, theta_group=None, theta_levels=None):
-        """Tree-walk accelerations [n,3] and potentials [n] (``bh_forces``, ``bh_forces_theta``, or with
-        theta_levels = (group_level, level_theta) ``bh_forces_theta_levels``)."""
+    def forces(self, theta=0.5, eps=0.0, acc=None, pot=None, theta_group=None):
+        """Tree-walk accelerations [n,3] and potentials [n] (``bh_forces`` / ``bh_forces_theta``)."""
         acc, pot = self._outs(acc, pot)
         lib = load()
-        if theta_levels is not None:
-            gl, arr, nl = self._theta_levels(theta_levels)
-            _check(lib.bh_forces_theta_levels(self._h, _ptr(gl), arr, nl, float(eps), _ptr(acc), _ptr(pot),
-                                              _stream(self.device)))
-            return acc, pot
         tg = self._theta_group(theta_group)
         if tg is None:
             _check(lib.bh_forces(self._h, float(theta), float(eps), _ptr(acc), _ptr(pot), _stream(self.device)))
@@ -344,7 +326,7 @@ class Tree:
                                        _stream(self.device)))
         return acc, pot
 
-    def walk_stats(self, theta=0.5, eps=0.0, theta_group=None, maxlen=0, theta_levels=None):
+    def walk_stats(self, theta=0.5, eps=0.0, theta_group=None, maxlen=0):
         """Forces plus per-particle (particle terms, cell terms), list hash, nodes visited per
         64-target group, and an optional list dump."""
         acc, pot = self._outs(None, None)
@@ -354,16 +336,10 @@ class Tree:
         lists = None
         if maxlen > 0:
             lists = torch.full((self.n, maxlen), -1, dtype=torch.int64, device=self.device)
-        if theta_levels is not None:
-            gl, arr, nl = self._theta_levels(theta_levels)
-            _check(load().bh_walk_stats_levels(self._h, _ptr(gl), arr, nl, float(eps), _ptr(acc), _ptr(pot),
-                                               _ptr(counts), _ptr(hsh), _ptr(lists), int(maxlen), _ptr(steps),
-                                               _stream(self.device)))
-        else:
-            tg = self._theta_group(theta_group)
-            _check(load().bh_walk_stats(self._h, float(theta), _ptr(tg), float(eps), _ptr(acc), _ptr(pot),
-                                        _ptr(counts), _ptr(hsh), _ptr(lists), int(maxlen), _ptr(steps),
-                                        _stream(self.device)))
+        tg = self._theta_group(theta_group)
+        _check(load().bh_walk_stats(self._h, float(theta), _ptr(tg), float(eps), _ptr(acc), _ptr(pot),
+                                    _ptr(counts), _ptr(hsh), _ptr(lists), int(maxlen), _ptr(steps),
+                                    _stream(self.device)))
         out = dict(acc=acc, pot=pot, counts=counts, hash=hsh, group_steps=steps)
         if lists is not None:
             out["lists"] = lists
@@ -458,19 +434,6 @@ class MLP:
         self.step += 1
         _check(load().bh_mlp_adam(_ptr(self.params), _ptr(grad), _ptr(self.m), _ptr(self.v), self.step, float(lr),
                                   float(beta1), float(beta2), float(eps), _ptr(self.wbf16), _stream(self.device)))
-
-
-def theta_quantize(theta_group, level_theta):
-    """Levels (uint8 device tensor) of the per-group theta values: the largest k with
-    level_theta[k] <= theta_group[g] (``bh_theta_quantize``)."""
-    g = int(theta_group.shape[0])
-    out = torch.empty((max(g, 1),), dtype=torch.uint8, device=theta_group.device)
-    tg = theta_group.contiguous()
-    if tg.dtype != torch.float32:
-        raise ValueError("theta_group must be float32")
-    arr = (ctypes.c_float * len(level_theta))(*[float(x) for x in level_theta])
-    _check(load().bh_theta_quantize(_ptr(tg), g, arr, len(level_theta), _ptr(out), _stream(tg.device)))
-    return out[:g]
 
 
 def build_tree(pos, mass, workspace=None):

@@ -72,8 +72,7 @@ const double kThetaCap = 1.15;  // largest learned theta handed to the walk (bel
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Carves the workspace; with base == nullptr it only measures.
-size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_t** rank, int32_t** queue,
-              bool levels = true) {
+size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_t** rank, int32_t** queue) {
   const size_t N = (size_t)(n > 0 ? n : 1);
   const size_t nodes = 2 * N;
   const size_t sort_tiles = (N + bh::kSortTile - 1) / bh::kSortTile;
@@ -136,9 +135,6 @@ size_t layout(int64_t n, int64_t K, int prec, char* base, bh::BuildWs* w, int32_
   t.hhist = reinterpret_cast<int32_t*>(take(4 * hist));
   t.hscan = reinterpret_cast<int32_t*>(take(4 * scan_tiles));
   t.qrec = reinterpret_cast<bh::QuadRec*>(take(sizeof(bh::QuadRec) * (nodes + 1)));
-  // (S arrays of the theta levels; the allocation-free entry point has none)
-  t.level_stride = (int64_t)up(8 * (nodes + 1)) / 8;
-  t.level_S = levels ? reinterpret_cast<double*>(take(8 * (size_t)t.level_stride * bh::kMaxThetaLevels)) : nullptr;
   int32_t* r = reinterpret_cast<int32_t*>(take(4 * N));
   if (w) *w = t;
   if (rank) *rank = r;
@@ -254,36 +250,11 @@ hipError_t ensure_target_order(const bh_tree* t, hipStream_t st) {
   return hipSuccess;
 }
 
-// Theta per walk group from a table of levels: group_level (device) indexes
-// level_theta (host).
-struct LevelArgs {
-  const uint8_t* group_level;
-  const float* level_theta;
-  int n_levels;
-};
-
-int check_levels(const bh_tree* t, const LevelArgs& lv) {
-  if (lv.n_levels < 1 || lv.n_levels > BH_MAX_THETA_LEVELS)
-    return fail(BH_EINVAL, "n_levels must be in [1, %d]; got %d", BH_MAX_THETA_LEVELS, lv.n_levels);
-  if (!lv.level_theta) return fail(BH_EINVAL, "level_theta must not be null");
-  for (int k = 0; k < lv.n_levels; ++k) {
-    const double th = (double)lv.level_theta[k];
-    if (!(th > 0.0 && th < bh::kThetaMax))
-      return fail(BH_EINVAL, "level_theta[%d] must be in (0, 2/sqrt(3)); got %g", k, th);
-  }
-  if (t->n > 0 && !lv.group_level) return fail(BH_EINVAL, "group_level must be a non-null device array");
-  return BH_OK;
-}
-
 int run_walk(const bh_tree* t, double theta, const float* theta_group, double eps, void* acc, void* pot,
              int mode, int32_t* counts, uint64_t* hash, int64_t* lists, int64_t maxlen, int32_t* group_steps,
-             hipStream_t st, bool allow_timing = true, const LevelArgs* lv = nullptr) {
+             hipStream_t st, bool allow_timing = true) {
   if (!t) return fail(BH_EINVAL, "null tree");
-  if (lv) {
-    int rc = check_levels(t, *lv);
-    if (rc) return rc;
-    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(BH_EINVAL, "eps must be finite and >= 0; got %g", eps);
-  } else if (!theta_group) {
+  if (!theta_group) {
     int rc = check_theta_eps(theta, eps);
     if (rc) return rc;
   } else if (!(eps >= 0.0) || !std::isfinite(eps)) {
@@ -297,39 +268,13 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
     return fail(BH_EINVAL, "counts/hash must be non-null aligned device arrays");
   if (mode == bh::kWalkDump && (!lists || maxlen <= 0 || !aligned(lists, 8)))
     return fail(BH_EINVAL, "lists must be a non-null aligned device array with maxlen > 0");
-  // Theta levels go their own way on FP32 walks of order 1 with one target
-  // per lane; other walks take the levels' values as per-group theta.
-  const bool level_path = lv && t->prec == BH_FP32 && t->order == 1 && t->targets_per_lane == 1;
-  bh::LevelInv inv{}, lth{};
-  uint32_t guard_bits = 0;
-  if (lv) {
-    for (int k = 0; k < lv->n_levels; ++k) {
-      lth.v[k] = (double)lv->level_theta[k];
-      inv.v[k] = 1.0 / (double)lv->level_theta[k];
-      if (lth.v[k] > 1.0) guard_bits |= 1u << k;
-    }
-  }
-  if (!theta_group && !lv) {
+  if (!theta_group) {
     hipError_t e = bh::launch_mac_size(t->w.nodes, t->w.counts, (int)(2 * t->n), 1.0 / theta, t->w.wnodes, st);
     if (e != hipSuccess) return hip_fail(e, "launching the opening-size pass");
   } else {
     // the flag reports this walk's per-group values only
     hipError_t e = bh::fill_i32(&t->w.counts->bad_theta, 1, 0, st);
     if (e != hipSuccess) return hip_fail(e, "clearing the theta flag");
-  }
-  if (lv && !level_path) {
-    // (the level array's memory holds the per-group values meanwhile)
-    float* tg = reinterpret_cast<float*>(t->w.level_S);
-    hipError_t e = bh::launch_level_theta(lv->group_level, (t->n + 63) / 64, lth, lv->n_levels, tg,
-                                          &t->w.counts->bad_theta, st);
-    if (e != hipSuccess) return hip_fail(e, "launching the level-to-theta pass");
-    theta_group = tg;
-  }
-  if (level_path) {
-    hipError_t e = bh::launch_level_copy(t->w.nodes, t->w.counts, (int)(2 * t->n), inv, lv->n_levels,
-                                         reinterpret_cast<bh::LevelNode*>(t->w.wnodes), t->w.level_S,
-                                         t->w.level_stride, st);
-    if (e != hipSuccess) return hip_fail(e, "launching the level walk copy");
   }
   if (theta_group && t->prec == BH_FP32) {
     hipError_t e = bh::launch_theta_copy(t->w.nodes, t->w.counts, (int)(2 * t->n),
@@ -363,16 +308,8 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.n_seg = (int)t->n_seg;
   a.n = (int)t->n;
   a.eps2 = eps * eps;
-  a.inv_theta = (theta_group || lv) ? 0.0 : 1.0 / theta;
+  a.inv_theta = theta_group ? 0.0 : 1.0 / theta;
   a.theta_group = theta_group;
-  if (level_path) {
-    a.lnodes = reinterpret_cast<const bh::LevelNode*>(t->w.wnodes);
-    a.level_S = t->w.level_S;
-    a.group_level = lv->group_level;
-    a.level_stride = t->w.level_stride;
-    a.n_levels = lv->n_levels;
-    a.level_guard = guard_bits;
-  }
   a.acc = acc;
   a.pot = pot;
   a.counts = counts;
@@ -383,7 +320,7 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
   a.xcd_chunk = t->xcd_chunk >= 0 ? t->xcd_chunk : (t->prec == BH_FP64 ? 0 : 1024);
   a.lds_share64 = t->lds_share64;
   a.waves_per_block = t->waves_per_block;
-  a.persistent = level_path ? 0 : t->persistent;  // (level walks: plain launches)
+  a.persistent = t->persistent;
   a.targets_per_lane = t->order == 2 ? 1 : t->targets_per_lane;  // (order 2: one target per lane)
   a.queue = t->queue;
   if (a.persistent) {
@@ -415,7 +352,6 @@ int run_walk(const bh_tree* t, double theta, const float* theta_group, double ep
 // once per device with that device current, and is the only one ever handed
 // to kernels.
 static_assert(BH_NOALLOC_SCRATCH_BYTES % kAlign == 0, "scratch size must keep the workspace alignment");
-static_assert(BH_MAX_THETA_LEVELS == bh::kMaxThetaLevels, "one limit on theta levels");
 static __device__ __align__(256) unsigned char scratch[BH_NOALLOC_SCRATCH_BYTES];
 
 std::mutex g_noalloc_mu;                 // guards the two tables below (host state only)
@@ -539,7 +475,7 @@ int bh_forces_noalloc(const void* pos, const void* mass, int64_t n, int prec, do
   if (!pos || !mass || !acc || !pot || !aligned(pos, el) || !aligned(mass, el) || !aligned(acc, el) ||
       !aligned(pot, el))
     return fail(BH_EINVAL, "pos/mass/acc/pot must be non-null device arrays aligned to %zu bytes", el);
-  const size_t need = layout(n, 1, prec, nullptr, nullptr, nullptr, nullptr, false);
+  const size_t need = layout(n, 1, prec, nullptr, nullptr, nullptr, nullptr);
   if (need > (size_t)BH_NOALLOC_SCRATCH_BYTES)
     return fail(BH_ENOSPC, "%zu bytes of scratch needed, %d held", need, BH_NOALLOC_SCRATCH_BYTES);
   int dev = 0;
@@ -558,7 +494,7 @@ int bh_forces_noalloc(const void* pos, const void* mass, int64_t n, int prec, do
   t.prec = prec;
   t.pos = pos;
   t.mass = mass;
-  layout(n, 1, prec, static_cast<char*>(base), &t.w, &t.rank, &t.queue, false);
+  layout(n, 1, prec, static_cast<char*>(base), &t.w, &t.rank, &t.queue);
   hipStream_t st = static_cast<hipStream_t>(stream);
   // every array the build and the walk read is written by them first (counters
   // and flags by fill kernels), so the previous call's contents do not matter
@@ -574,43 +510,6 @@ int bh_walk_stats(const bh_tree* t, double theta, const float* theta_group, doub
   if (group_steps && !aligned(group_steps, 4)) return fail(BH_EINVAL, "group_steps must be 4-byte aligned");
   return run_walk(t, theta, theta_group, eps, acc, pot, lists ? bh::kWalkDump : bh::kWalkStats, counts, hash,
                   lists, maxlen, group_steps, static_cast<hipStream_t>(stream));
-}
-
-int bh_forces_theta_levels(const bh_tree* t, const uint8_t* group_level, const float* level_theta, int n_levels,
-                           double eps, void* acc, void* pot, void* stream) {
-  const LevelArgs lv{group_level, level_theta, n_levels};
-  return run_walk(t, 0.0, nullptr, eps, acc, pot, bh::kWalkForces, nullptr, nullptr, nullptr, 0, nullptr,
-                  static_cast<hipStream_t>(stream), true, &lv);
-}
-
-int bh_walk_stats_levels(const bh_tree* t, const uint8_t* group_level, const float* level_theta, int n_levels,
-                         double eps, void* acc, void* pot, int32_t* counts, uint64_t* hash, int64_t* lists,
-                         int64_t maxlen, int32_t* group_steps, void* stream) {
-  if (group_steps && !aligned(group_steps, 4)) return fail(BH_EINVAL, "group_steps must be 4-byte aligned");
-  const LevelArgs lv{group_level, level_theta, n_levels};
-  return run_walk(t, 0.0, nullptr, eps, acc, pot, lists ? bh::kWalkDump : bh::kWalkStats, counts, hash, lists,
-                  maxlen, group_steps, static_cast<hipStream_t>(stream), true, &lv);
-}
-
-int bh_theta_quantize(const float* theta_group, int64_t groups, const float* level_theta, int n_levels,
-                      uint8_t* group_level, void* stream) {
-  if (groups < 0 || groups > kMaxN) return fail(BH_EINVAL, "groups must be in [0, 2^30 - 1]");
-  if (n_levels < 1 || n_levels > BH_MAX_THETA_LEVELS)
-    return fail(BH_EINVAL, "n_levels must be in [1, %d]; got %d", BH_MAX_THETA_LEVELS, n_levels);
-  if (!level_theta) return fail(BH_EINVAL, "level_theta must not be null");
-  bh::LevelInv lth{};
-  for (int k = 0; k < n_levels; ++k) {
-    lth.v[k] = (double)level_theta[k];
-    if (!std::isfinite(lth.v[k]) || (k > 0 && !(lth.v[k] > lth.v[k - 1])))
-      return fail(BH_EINVAL, "level_theta must be finite and strictly increasing");
-  }
-  if (groups == 0) return BH_OK;
-  if (!theta_group || !group_level || !aligned(theta_group, 4))
-    return fail(BH_EINVAL, "theta_group/group_level must be non-null device arrays");
-  hipError_t e = bh::launch_theta_quantize(theta_group, groups, lth, n_levels, group_level,
-                                           static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "launching the theta quantisation");
-  return BH_OK;
 }
 
 int bh_tree_export(const bh_tree* t, void* nodes, int32_t* perm, void* stream) {

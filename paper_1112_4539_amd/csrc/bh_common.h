@@ -73,25 +73,6 @@ struct alignas(64) ThetaNode {
 };
 static_assert(sizeof(ThetaNode) == 64, "ThetaNode must be 64 bytes");
 
-// The walk's copy of a node for walks with one theta per walk group taken from
-// a table of levels: everything of WalkNode but S, which each level keeps in
-// an array of its own (S_k[c] = (l/theta_k + s)^2, a leaf 0), so that a wave
-// reads its node's centre, FP32 mass and next in one load and its level's S
-// in a second, as in a walk with one theta.
-struct alignas(64) LevelNode {
-  double cx, cy, cz;
-  float M32;
-  int32_t next;
-  int32_t first;
-  int32_t count;
-  int32_t meta;
-  int32_t pad;
-  double M;
-  double pad2;
-};
-static_assert(sizeof(LevelNode) == 64, "LevelNode must be 64 bytes");
-constexpr int kMaxThetaLevels = 16;
-
 // Second moments of a node for walks of order 2 (quadrupole cell terms):
 // B_ab = sum over the node's particles of m (x_a - com_a)(x_b - com_b), FP64,
 // with T = Bxx + Byy + Bzz kept as T/2 (exact) and -3T/2, the two forms the

@@ -72,8 +72,6 @@ struct BuildWs {
   int32_t* hhist;           // [256 * ntiles]
   int32_t* hscan;           // scan scratch
   QuadRec* qrec;            // [2n + 1] second moments of every node (walks of order 2; filled on demand)
-  double* level_S;          // [kMaxThetaLevels][level_stride] S of each theta level (walks with theta levels)
-  int64_t level_stride;     // >= 2n + 1
 };
 
 // A second stream for a build: the Hilbert walk order, which needs only the
@@ -124,12 +122,6 @@ struct WalkArgs {
   const ThetaNode* tnodes;     // per-group theta, FP32: walk copy with l and s (same memory as wnodes)
   const float* theta_group;    // theta per walk group (64 targets of the walk order), may be null
   const QuadRec* qrec;         // order 2: second moments of every node (cell terms with the quadrupole)
-  const LevelNode* lnodes;     // theta levels: walk copy without S (same memory as wnodes), or null
-  const double* level_S;       // theta levels: S of level k for node c at level_S[k * level_stride + c]
-  const uint8_t* group_level;  // theta levels: level of every walk group
-  int64_t level_stride;
-  int n_levels;
-  uint32_t level_guard;        // theta levels: bit k set if theta_k > 1 (cells can hold their target)
   void* acc;                   // [n][3] caller order
   void* pot;                   // [n] caller order
   int32_t* counts;             // stats: [n][2] = (particle terms, cell terms), caller order
@@ -149,8 +141,6 @@ struct WalkArgs {
 enum WalkMode { kWalkForces = 0, kWalkStats = 1, kWalkDump = 2 };
 // Added to a mode: cell terms of order 2 (monopole plus quadrupole correction).
 constexpr int kWalkQuad = 4;
-// Added to a mode: theta per walk group from a table of levels (a.lnodes, a.level_S).
-constexpr int kWalkLevel = 8;
 
 hipError_t launch_walk(bool f64, int mode, const WalkArgs& a, hipStream_t st);
 
@@ -192,20 +182,6 @@ hipError_t launch_mlp_adam(float* P, const float* grad, float* m, float* v, floa
 
 // Walk copy of the nodes for per-group theta (FP32 walks).
 hipError_t launch_theta_copy(const Node* nodes, const Counts* counts, int cap, ThetaNode* tnodes, hipStream_t st);
-
-// Walk copy for theta levels: level records (lnodes, 2n + 1) and the S arrays
-// of the levels (S[k * stride + c]) from 1/theta_k.
-struct LevelInv {
-  double v[kMaxThetaLevels];
-};
-hipError_t launch_level_copy(const Node* nodes, const Counts* counts, int cap, const LevelInv& inv, int n_levels,
-                             LevelNode* lnodes, double* S, int64_t stride, hipStream_t st);
-// theta_group[g] = level_theta[group_level[g]] (a level out of range: 0 and bad_theta set).
-hipError_t launch_level_theta(const uint8_t* group_level, int64_t groups, const LevelInv& theta, int n_levels,
-                              float* theta_group, int32_t* bad_theta, hipStream_t st);
-// group_level[g] = the largest k with level_theta[k] <= theta_group[g] (levels ascending; 0 below the first).
-hipError_t launch_theta_quantize(const float* theta_group, int64_t groups, const LevelInv& theta, int n_levels,
-                                 uint8_t* group_level, hipStream_t st);
 
 // Neighbour search (the general tree walk of Fig. 4): per target the particles
 // within `radius`, their ordered hash, optional lists and the SPH density.

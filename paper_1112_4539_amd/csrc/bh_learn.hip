@@ -1,7 +1,7 @@
 // bh_learn.hip -- the learned opening parameter (gfx950): group features, the
 // per-group force error that labels them, and the small MLP that maps features
 // to theta, with its training step.  None of this is in the paper: the paper
-// uses one fixed theta (Eq. (2)); here each Morton group of 64 targets may get
+// uses one fixed theta (Eq. (2)); here each walk group of 64 targets may get
 // its own, predicted from the group's geometry and the tree around it.
 //
 // MLP: 8 -> 64 -> 64 -> 1, tanh-form GELU, theta = 0.2 + 0.8 sigmoid(z).

@@ -67,84 +67,6 @@ hipError_t launch_theta_copy(const Node* nodes, const Counts* counts, int cap, T
   return hipGetLastError();
 }
 
-// Walk copy for theta levels: the level record of every node and, per level
-// k, S_k = (l/theta_k + s)^2 for a cell (formed as in the per-group-theta
-// step, from 1/theta_k) and 0 for a leaf.
-__global__ __launch_bounds__(256) void k_level_copy(const Node* __restrict__ nodes, const Counts* __restrict__ cnt,
-                                                    int cap, LevelInv inv, int n_levels,
-                                                    LevelNode* __restrict__ lnodes, double* __restrict__ S,
-                                                    int64_t stride) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cap || c >= cnt->n_nodes) return;
-  const Node nd = nodes[c];
-  const bool leaf = nd.meta & 1;
-  LevelNode w;
-  w.cx = nd.cx;
-  w.cy = nd.cy;
-  w.cz = nd.cz;
-  w.M32 = (float)nd.M;
-  w.next = min(max(nd.next, c + 1), cap);  // as in the uniform-theta copy
-  w.first = nd.first;
-  w.count = nd.count;
-  w.meta = nd.meta;
-  w.pad = 0;
-  w.M = nd.M;
-  w.pad2 = 0.0;
-  lnodes[c] = w;
-  for (int k = 0; k < n_levels && k < kMaxThetaLevels; ++k) {
-    const double u = fma(leaf ? 0.0 : nd.l, inv.v[k], leaf ? 0.0 : nd.s);
-    S[k * stride + c] = u * u;
-  }
-}
-
-hipError_t launch_level_copy(const Node* nodes, const Counts* counts, int cap, const LevelInv& inv, int n_levels,
-                             LevelNode* lnodes, double* S, int64_t stride, hipStream_t st) {
-  if (cap <= 0) return hipSuccess;
-  k_level_copy<<<(cap + 255) / 256, 256, 0, st>>>(nodes, counts, cap, inv, n_levels, lnodes, S, stride);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_level_theta(const uint8_t* __restrict__ group_level, int64_t groups,
-                                                     LevelInv theta, int n_levels, float* __restrict__ theta_group,
-                                                     int32_t* __restrict__ bad_theta) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= groups) return;
-  int k = group_level[g];
-  if (k >= n_levels) {
-    atomicOr(bad_theta, 1);
-    k = 0;
-  }
-  theta_group[g] = (float)theta.v[k];
-}
-
-hipError_t launch_level_theta(const uint8_t* group_level, int64_t groups, const LevelInv& theta, int n_levels,
-                              float* theta_group, int32_t* bad_theta, hipStream_t st) {
-  if (groups <= 0) return hipSuccess;
-  k_level_theta<<<(int)((groups + 255) / 256), 256, 0, st>>>(group_level, groups, theta, n_levels, theta_group,
-                                                             bad_theta);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_theta_quantize(const float* __restrict__ theta_group, int64_t groups,
-                                                        LevelInv theta, int n_levels,
-                                                        uint8_t* __restrict__ group_level) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= groups) return;
-  const double th = (double)theta_group[g];
-  int k = 0;
-  if (isfinite(th))
-    for (int j = 1; j < n_levels && j < kMaxThetaLevels; ++j)
-      if (theta.v[j] <= th) k = j;
-  group_level[g] = (uint8_t)k;
-}
-
-hipError_t launch_theta_quantize(const float* theta_group, int64_t groups, const LevelInv& theta, int n_levels,
-                                 uint8_t* group_level, hipStream_t st) {
-  if (groups <= 0) return hipSuccess;
-  k_theta_quantize<<<(int)((groups + 255) / 256), 256, 0, st>>>(theta_group, groups, theta, n_levels, group_level);
-  return hipGetLastError();
-}
-
 // Workgroups of the persistent walk that are resident on the chip at once (0 if
 // the runtime cannot tell).
 int persistent_grid(bool f64, int mode, bool soft, bool group_theta, int waves_per_block, int targets_per_lane) {

@@ -274,58 +274,6 @@ struct StepNode<true, true> {
   __device__ __forceinline__ Node load_at(int c) const { return const_load(base, c); }
 };
 
-// What a step of a walk with theta levels reads: the level copy's record and
-// the wave's level's S of the node.
-struct LevelStep {
-  double cx, cy, cz;
-  double S;
-  float M32;
-  int32_t next;
-  int32_t first;
-  int32_t count;
-  int32_t meta;
-  int32_t pad;
-  double M;
-};
-struct StepLevel {
-  const LevelNode* base;
-  const double* S;   // the wave's level: S of node c at S[c]
-  __device__ __forceinline__ LevelStep load(int c) const {
-    const BH_CONST LevelNode* p = (const BH_CONST LevelNode*)(uintptr_t)base + (uint32_t)c;
-    LevelStep r;
-    r.cx = p->cx; r.cy = p->cy; r.cz = p->cz; r.M32 = p->M32; r.next = p->next;
-    r.first = p->first; r.count = p->count; r.meta = p->meta; r.pad = 0; r.M = p->M;
-    r.S = *((const BH_CONST double*)(uintptr_t)S + (uint32_t)c);
-    return r;
-  }
-  template <bool kOff32>
-  __device__ __forceinline__ LevelStep load_at(int c) const {
-    if constexpr (!kOff32) return load(c);
-    const BH_CONST char* b = rec_at32(base, c);
-    // (M32 and next as a pair of their own: a single element taken out of the
-    // eight-dword vector was compiled as its first dword)
-    const v8u_t w0 = *(const BH_CONST v8u_t*)b;             // cx, cy, cz
-    const v2u_t w1 = *(const BH_CONST v2u_t*)(b + 24);      // M32, next
-    const v2u_t w2 = *(const BH_CONST v2u_t*)(b + 32);      // first, count
-    const v2u_t w3 = *(const BH_CONST v2u_t*)(b + 40);      // meta, pad
-    const v2u_t w4 = *(const BH_CONST v2u_t*)(b + 48);      // M
-    const v2u_t ws = *(const BH_CONST v2u_t*)((const BH_CONST char*)(uintptr_t)S + (uint32_t)c * 8u);
-    LevelStep r;
-    r.cx = f64_of(w0.s01);
-    r.cy = f64_of(w0.s23);
-    r.cz = f64_of(w0.s45);
-    r.M32 = __builtin_bit_cast(float, w1.x);
-    r.next = (int)w1.y;
-    r.first = (int)w2.x;
-    r.count = (int)w2.y;
-    r.meta = (int)w3.x;
-    r.pad = 0;
-    r.M = f64_of(w4);
-    r.S = f64_of(ws);
-    return r;
-  }
-};
-
 // Per-target state of a walk.
 template <bool kF64>
 struct Target {
@@ -503,8 +451,7 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
     // (the walk copies mark a leaf by S = 0, resp. l = 0, so their steps need
     // no meta word to tell cells from leaves)
     bool cell;
-    if constexpr (std::is_same<Rec, WalkNode>::value || std::is_same<Rec, LevelStep>::value)
-      cell = __builtin_bit_cast(uint64_t, cur.S) != 0;
+    if constexpr (std::is_same<Rec, WalkNode>::value) cell = __builtin_bit_cast(uint64_t, cur.S) != 0;
     else if constexpr (std::is_same<Rec, ThetaNode>::value) cell = __builtin_bit_cast(uint64_t, cur.l) != 0;
     else cell = (cur.meta & 1) == 0;
     // FP32: the term's factors are formed for every lane ahead of the masked
@@ -585,9 +532,9 @@ __device__ __forceinline__ void fetch_pair(const Rec* base, int ca, int cb, int 
 // the node capacity, so a corrupted record can never send the cursor out of the
 // array, and every step moves the cursor forward or stays on a leaf for at most
 // its particle count.
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, bool kOff32,
-          typename WN>
-__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, WN wn, Cursor<kF64, kT>& C, int end) {
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, bool kOff32>
+__device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
+                                                 int end) {
   using Rec = decltype(wn.load(0));
   // The next record is read before the loop test: the walk copies have a spare
   // record at index cap = 2n (their next pointers stay <= cap); the plain node
@@ -616,9 +563,9 @@ __device__ __forceinline__ void walk_loop_scalar(const WalkArgs& a, WN wn, Curso
   }
 }
 
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, typename WN>
-__device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, WN wn, Cursor<kF64, kT>& C, uint4 (*pf)[8],
-                                              int end) {
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket>
+__device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
+                                              uint4 (*pf)[8], int end) {
   using Rec = decltype(wn.load(0));
   const int cap = 2 * a.n;
   const int lane = __lane_id();
@@ -643,10 +590,9 @@ __device__ __forceinline__ void walk_loop_lds(const WalkArgs& a, WN wn, Cursor<k
 
 // The clusters klo..khi of a wave, one subtree after the other; targets of the
 // other clusters stay idle (skip past the subtree).
-template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, bool kLds,
-          typename WN>
-__device__ __forceinline__ void walk_clusters(const WalkArgs& a, WN wn, Cursor<kF64, kT>& C, uint4 (*pf)[8],
-                                              const int (&kc)[kT], int klo, int khi) {
+template <bool kF64, int kT, int kMode, bool kSoft, bool kPlain, bool kGuard, bool kBucket, bool kLds>
+__device__ __forceinline__ void walk_clusters(const WalkArgs& a, StepNode<kF64, kPlain> wn, Cursor<kF64, kT>& C,
+                                              uint4 (*pf)[8], const int (&kc)[kT], int klo, int khi) {
   const int cap = 2 * a.n;
   // (the plain nodes of the FP64 per-group-theta walk keep 64-bit addressing)
   constexpr bool kRaw = kF64 && kPlain;
@@ -659,7 +605,7 @@ __device__ __forceinline__ void walk_clusters(const WalkArgs& a, WN wn, Cursor<k
 #pragma unroll
     for (int t = 0; t < kT; ++t) C.t[t].skip = (C.t[t].i >= 0 && kc[t] == k) ? r0 : 0x7fffffff;
     if (r0 >= r1) continue;
-    if constexpr (kLds && (kMode & (kWalkQuad | kWalkLevel)) == 0)
+    if constexpr (kLds && (kMode & kWalkQuad) == 0)
       walk_loop_lds<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket>(a, wn, C, pf, r1);
     else if (off32)
       walk_loop_scalar<kF64, kT, kMode, kSoft, kPlain, kGuard, kBucket, true>(a, wn, C, r1);
@@ -670,28 +616,15 @@ __device__ __forceinline__ void walk_clusters(const WalkArgs& a, WN wn, Cursor<k
 
 // The walk of one group of 64 kT targets (one wavefront).
 // kSoft: eps > 0, so r^2 + eps^2 > 0 and the FP32 term needs no zero test.
-// kGroupTheta: theta per 64-particle Morton group instead of one uniform theta
+// kGroupTheta: theta per walk group (64 targets) instead of one uniform theta
 // (uniform theta walks the copy with S precomputed).
 template <bool kF64, int kT, int kMode, bool kSoft, bool kGroupTheta>
 __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (*pf)[8]) {
   using R = typename Cursor<kF64, kT>::R;
   using R4 = typename std::conditional<kF64, double4, float4>::type;
   constexpr bool kStats = (kMode & 3) != kWalkForces;
-  // theta levels: the wave is one walk group (one target per lane), whose
-  // level picks the S array it reads; an out-of-range level is replaced by
-  // level 0 and reported
-  constexpr bool kLevel = (kMode & kWalkLevel) != 0;
-  static_assert(!kLevel || (kT == 1 && !kF64 && !kGroupTheta), "theta levels: FP32, one target per lane");
   const int lane = __lane_id();
   const R4* __restrict__ ps = reinterpret_cast<const R4*>(a.ps);
-  int lev = 0;
-  if constexpr (kLevel) {
-    lev = (int64_t)group * kWave < a.n ? uniform((int)a.group_level[group]) : 0;
-    if (lev >= a.n_levels) {
-      if (lane == 0) atomicOr(a.bad_theta, 1);
-      lev = 0;
-    }
-  }
 
   Cursor<kF64, kT> C;
   C.k = C.kend = 0;
@@ -743,64 +676,56 @@ __device__ __forceinline__ void walk_group(const WalkArgs& a, int group, uint4 (
     T.node0 = valid ? a.croot[kc[t]] : 0;
     T.idx0 = valid ? (int)a.seg_off[kc[t]] : 0;
   }
-  const bool guard = kLevel ? ((a.level_guard >> lev) & 1u) != 0 : ballot(guard_l) != 0ull;
+  const bool guard = ballot(guard_l) != 0ull;
   for (int o = 32; o > 0; o >>= 1) {
     klo = min(klo, __shfl_xor(klo, o, 64));
     khi = max(khi, __shfl_xor(khi, o, 64));
   }
   klo = uniform(klo);
   khi = uniform(khi);
+  StepNode<kF64, kGroupTheta> wn;
+  if constexpr (kGroupTheta && kF64) wn.base = a.nodes;
+  else if constexpr (kGroupTheta) wn.base = a.tnodes;
+  else wn.base = a.wnodes;
   // Waves split between the two node paths (scalar cache / LDS copies) so
   // that neither the scalar cache nor instruction issue alone sets the pace;
   // the share taking the LDS path is a launch parameter (results identical).
   // (taken as a wave-uniform value: the compiler cannot tell that the wave
   // index is uniform, and a branch it took for divergent would turn the walk
   // state that crosses it into per-lane values)
-  // (walks of order 2 and walks with theta levels take the scalar route only)
-  const bool lds_path =
-      (kMode & (kWalkQuad | kWalkLevel)) == 0 && uniform(((group * 37) & 63) < a.lds_share64 ? 1 : 0) != 0;
+  // (walks of order 2 take the scalar route only)
+  const bool lds_path = (kMode & kWalkQuad) == 0 && uniform(((group * 37) & 63) < a.lds_share64 ? 1 : 0) != 0;
+  // (one cluster loop per path and guard: the LDS path's copies must not share
+  // a loop with the scalar path's loads, or the compiler stops treating the
+  // node array as unwritten and drops the scalar loads)
   // Leaves of several coincident-key particles exist iff some keys repeat
   // (fewer leaves than particles); without them the step needs no branch for
   // them.
   const bool buckets = uniform(a.cnt->n_unique < a.n ? 1 : 0) != 0;
-  // (one cluster loop per path and guard: the LDS path's copies must not share
-  // a loop with the scalar path's loads, or the compiler stops treating the
-  // node array as unwritten and drops the scalar loads)
-  auto run = [&](auto wn) {
-    if (lds_path) {
-      if (buckets) {
-        if (guard)
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true, true>(a, wn, C, pf, kc, klo, khi);
-        else
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true, true>(a, wn, C, pf, kc, klo, khi);
-      } else {
-        if (guard)
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false, true>(a, wn, C, pf, kc, klo, khi);
-        else
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false, true>(a, wn, C, pf, kc, klo, khi);
-      }
+  if (lds_path) {
+    if (buckets) {
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true, true>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true, true>(a, wn, C, pf, kc, klo, khi);
     } else {
-      if (buckets) {
-        if (guard)
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true, false>(a, wn, C, pf, kc, klo, khi);
-        else
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true, false>(a, wn, C, pf, kc, klo, khi);
-      } else {
-        if (guard)
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false, false>(a, wn, C, pf, kc, klo, khi);
-        else
-          walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false, false>(a, wn, C, pf, kc, klo, khi);
-      }
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false, true>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false, true>(a, wn, C, pf, kc, klo, khi);
     }
-  };
-  if constexpr (kLevel) {
-    run(StepLevel{a.lnodes, a.level_S + (int64_t)lev * a.level_stride});
   } else {
-    StepNode<kF64, kGroupTheta> wn;
-    if constexpr (kGroupTheta && kF64) wn.base = a.nodes;
-    else if constexpr (kGroupTheta) wn.base = a.tnodes;
-    else wn.base = a.wnodes;
-    run(wn);
+    if (buckets) {
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, true, false>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, true, false>(a, wn, C, pf, kc, klo, khi);
+    } else {
+      if (guard)
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, true, false, false>(a, wn, C, pf, kc, klo, khi);
+      else
+        walk_clusters<kF64, kT, kMode, kSoft, kGroupTheta, false, false, false>(a, wn, C, pf, kc, klo, khi);
+    }
   }
 
 #pragma unroll
@@ -877,13 +802,9 @@ static hipError_t launch_t(const WalkArgs& a, hipStream_t st) {
 template <bool kF64, int kT, int kMode>
 static hipError_t launch_mode(const WalkArgs& a, hipStream_t st) {
   const bool soft = a.eps2 > 0.0;
-  if constexpr ((kMode & kWalkLevel) != 0) {
-    return soft ? launch_t<kF64, kT, kMode, true, false>(a, st) : launch_t<kF64, kT, kMode, false, false>(a, st);
-  } else {
-    if (a.theta_group)
-      return soft ? launch_t<kF64, kT, kMode, true, true>(a, st) : launch_t<kF64, kT, kMode, false, true>(a, st);
-    return soft ? launch_t<kF64, kT, kMode, true, false>(a, st) : launch_t<kF64, kT, kMode, false, false>(a, st);
-  }
+  if (a.theta_group)
+    return soft ? launch_t<kF64, kT, kMode, true, true>(a, st) : launch_t<kF64, kT, kMode, false, true>(a, st);
+  return soft ? launch_t<kF64, kT, kMode, true, false>(a, st) : launch_t<kF64, kT, kMode, false, false>(a, st);
 }
 
 template <bool kF64, int kT, int kMode>
@@ -900,10 +821,6 @@ static const void* persistent_fn(bool soft, bool group_theta) {
 // (walks of order 2 take one target per lane)
 template <bool kF64, int kMode>
 static hipError_t launch_walk_mode(const WalkArgs& a, hipStream_t st) {
-  // (theta levels: FP32 walks of order 1, one target per lane; the API turns
-  // other level walks into per-group-theta walks)
-  if constexpr (!kF64)
-    if (a.lnodes) return launch_mode<kF64, 1, kMode | kWalkLevel>(a, st);
   if (a.qrec) return launch_mode<kF64, 1, kMode | kWalkQuad>(a, st);
   if (a.targets_per_lane == 2) return launch_mode<kF64, 2, kMode>(a, st);
   return launch_mode<kF64, 1, kMode>(a, st);

@@ -1,8 +1,8 @@
 """Trains the opening-parameter network shipped as weights/theta_clumpy4m.json.
 
-Recipe (run on the GPU: ``python -m paper_1112_4539_amd.train_theta``): eight clumpy fields of
-4,194,304 particles (the field recipe of the headline workload, seeds 300-307, eps 1e-4; the
-headline field itself, seed 2, is not among them), 2048 sampled Morton groups of each labelled
+Recipe (run on the GPU: ``python -m paper_1112_4539_amd.train_theta``): 32 clumpy fields of
+4,194,304 particles (the field recipe of the headline workload, seeds 300-331, eps 1e-4; the
+headline field itself, seed 2, is not among them), 4096 sampled walk groups of each labelled
 with the cost-optimal allocation at RMS 1e-3 (learn.label_sampled), then 80 epochs of Adam on
 batches of 1024 (learn.train).  Labels, features and training all run in the library's kernels;
 the result is deterministic for a given library build up to the order of floating-point
@@ -21,8 +21,8 @@ from paper_1112_4539_amd import learn
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--n", type=int, default=4194304)
-    ap.add_argument("--seeds", type=int, nargs=2, default=(300, 308), metavar=("FIRST", "END"))
-    ap.add_argument("--groups", type=int, default=2048)
+    ap.add_argument("--seeds", type=int, nargs=2, default=(300, 332), metavar=("FIRST", "END"))
+    ap.add_argument("--groups", type=int, default=4096)
     ap.add_argument("--epochs", type=int, default=80)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--out", default=learn.DEFAULT_WEIGHTS)

@@ -78,19 +78,3 @@ def test_host_side_argument_checks():
 def test_theta_bound_matches_header():
     import paper_1112_4539_amd as bh
     assert abs(bh.THETA_MAX - 2 / 3 ** 0.5) < 1e-15
-
-
-def test_theta_level_argument_checks():
-    """Theta levels: table size and values are checked on the host before any device work."""
-    import paper_1112_4539_amd as bh
-    lib = bh.load()
-    F = ctypes.c_float
-    ok = (F * 3)(0.3, 0.5, 0.7)
-    assert lib.bh_theta_quantize(None, 0, ok, 3, None, None) == 0            # nothing to do
-    assert lib.bh_theta_quantize(None, 5, ok, 0, None, None) == -1            # no levels
-    assert lib.bh_theta_quantize(None, 5, (F * 17)(*[0.1 + 0.05 * k for k in range(17)]), 17, None, None) == -1
-    assert lib.bh_theta_quantize(None, 5, (F * 3)(0.3, 0.3, 0.7), 3, None, None) == -1   # not increasing
-    assert b"increasing" in lib.bh_last_error()
-    assert lib.bh_theta_quantize(None, 5, ok, 3, None, None) == -1            # null arrays
-    assert lib.bh_forces_theta_levels(None, None, ok, 3, 1e-4, None, None, None) == -1
-    assert lib.bh_walk_stats_levels(None, None, ok, 3, 1e-4, None, None, None, None, None, 0, None, None) == -1

@@ -23,5 +23,6 @@ def test_shipped_weights_well_formed():
     p = np.asarray(rec["params"], np.float64)
     assert np.array_equal(p.astype(np.float32).astype(np.float64), p)
     info = rec["info"]
-    assert "seeds 300-307" in info["fields"] and info["label_target_rms"] == 1e-3
+    assert "seeds 300-331" in info["fields"] and info["label_target_rms"] == 1e-3
+    assert info["sampled_groups_per_field"] == 4096 and info["rows"] == 32 * 4096
     assert info["loss_first_last"][1] < info["loss_first_last"][0]
