@@ -1321,7 +1321,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_quad_chunk(const Counts* __re
       int c = i + 1;
       for (int k = 0; k < 8 && c < end; ++k, c = max(ci.nx[c] - c0, c + 1))
         quad_fold(b, sb[c], sc[c][0], sc[c][1], sc[c][2], sc[c][3], sc[i][0], sc[i][1], sc[i][2]);
-      for (int t = 0; t < 6; ++t) sb[i][t] = b[t];
+      for (int q = 0; q < 6; ++q) sb[i][q] = b[q];
     }
     __syncthreads();
   }

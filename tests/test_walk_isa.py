@@ -111,5 +111,6 @@ def test_group_theta_walk_loop(asm):
     # into a vector register (an instruction reads at most one scalar operand, and l and s both
     # come from the scalar record) per step
     assert valu[0] <= 48 and valu[-1] <= 53, f"per-group-theta step loops: {valu} VALU per two steps (designed: 48)"
-    assert min(c["smem"] for c in hot) <= 4, "the step reads its record in more than two scalar loads"
+    # (the record's centre, l, mass and next in two loads, s in a third)
+    assert min(c["smem"] for c in hot) <= 6, "the step reads its record in more than three scalar loads"
     assert "; ScratchSize: 0" in meta
