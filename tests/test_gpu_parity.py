@@ -143,6 +143,22 @@ def test_lists_and_forces_plummer4k_fp32(bh, theta, tpl):
     assert pot_err(pot, w["pot"]).max() <= F32_TOL
 
 
+@pytest.mark.parametrize("prec,tpl", [("fp64", 1), ("fp32", 1), ("fp32", 2)])
+def test_unsoftened(bh, prec, tpl):
+    """eps = 0, the unsoftened pair term of Eq. (1) (the walk's variant without softening): full
+    list dumps and forces against the oracle, with a leaf of five coincident particles, which add
+    nothing to each other (a pair at r = 0 has no defined force without softening)."""
+    say(f"[walk] plummer4k {prec} eps=0 full list dump, {tpl} targets per lane")
+    pos, mass = inputs.plummer(4096, 0)
+    pos = pos.copy()
+    pos[100:104] = pos[99]
+    acc, pot, w = _walk_compare(bh, pos, mass, prec, 0.5, 0.0, maxlen=4096, tpl=tpl)
+    assert np.all(np.isfinite(acc)) and np.all(np.isfinite(pot))
+    tol = F32_TOL if prec == "fp32" else F64_TOL
+    check_forces(acc, w["acc"], w["amag"], tol, f"eps=0 {prec}", log=say)
+    assert pot_err(pot, w["pot"]).max() <= tol
+
+
 @pytest.mark.parametrize("prec,theta", [("fp64", 1.1), ("fp32", 1.1), ("fp32", 1.15)])
 def test_lists_theta_above_one(bh, prec, theta):
     """theta in (1, 2/sqrt(3)): a cell holding the target can pass the opening

@@ -103,6 +103,18 @@ def test_quad_walk_plummer4k(bh, prec, theta):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_quad_walk_unsoftened(bh, prec):
+    say(f"[quad] plummer4k {prec} eps=0 full list dump")
+    pos, mass = inputs.plummer(4096, 0)
+    pos = pos.copy()
+    pos[100:104] = pos[99]
+    acc, pot, w = _walk_compare(bh, pos, mass, prec, 0.6, 0.0, maxlen=4096)
+    tol = F32_TOL if prec == "fp32" else F64_TOL
+    check_forces(acc, w["acc"], w["amag"], tol, f"quad eps=0 {prec}", log=say)
+    assert pot_err(pot, w["pot"]).max() <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_quad_walk_per_group_theta(bh, prec):
     say(f"[quad] clumpy 50k per-group theta {prec}")
     pos, mass = inputs.clumpy(50_000, 31)
