@@ -691,7 +691,8 @@ def main():
         "data": "synthetic",
         "config": {
             "precision": "FP32 positions, masses and outputs; FP32 terms (r^2+eps^2 rounded once, v_rsq_f32, FP32 "
-                         "products); FP64 offsets, opening test and sums",
+                         "products; the potential's m/r as (m/r^3)(r^2+eps^2) in its FP64 fused sum); FP64 offsets, "
+                         "opening test and sums",
             "workload": f"clumpy field N={n} (25% uniform in the unit cube + 64 Plummer clumps a=0.01, R=0.1), "
                         f"seed {spec['seed']}, eps={eps}, theta={args.theta}, FP32 in/out",
             "n": n, "theta": args.theta, "eps": eps,

@@ -49,6 +49,7 @@ namespace bh {
 struct MixedTerm {
   double mr3, mr;  // m r^-3 and m r^-1
   float ri;        // r^-1 (softened)
+  double r2;       // r^2 + eps^2 before its FP32 rounding
 };
 
 // Quadrupole correction of a cell term (walks of order 2): the second-order
@@ -89,13 +90,17 @@ struct AccMixed {
     // r2 == 0 only for a coincident pair without softening: that pair adds nothing
     const float ri = kSoft ? __builtin_amdgcn_rsqf(r2) : ((r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f);
     const float mr = m * ri;
-    return MixedTerm{(double)((mr * ri) * ri), (double)mr, ri};
+    return MixedTerm{(double)((mr * ri) * ri), (double)mr, ri, d2 + eps2};
   }
+  // (the monopole potential's m r^-1 is taken as (m r^-3)(r^2 + eps^2) in one
+  // FP64 fused multiply-add, which spares the term a conversion: with r^-1 from
+  // v_rsq_f32 good to about 1e-7, the product carries about three times that
+  // relative error, far inside the FP32 tolerance)
   __device__ __forceinline__ void add(const MixedTerm& q, double dx, double dy, double dz) {
     ax = fma(q.mr3, dx, ax);
     ay = fma(q.mr3, dy, ay);
     az = fma(q.mr3, dz, az);
-    p -= q.mr;
+    p = fma(-q.mr3, q.r2, p);
   }
   // a cell term of order 2: the monopole factors of `q` plus the correction `u`
   __device__ __forceinline__ void add_quad(const MixedTerm& q, const QuadPart& u, double dx, double dy, double dz) {
@@ -462,7 +467,10 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
 #pragma unroll
       for (int t = 0; t < kT; ++t) {
         q[t] = AccMixed::prep<kSoft>(d2[t], tm, a.eps2);
-        asm volatile("" : "+v"(q[t].mr3), "+v"(q[t].mr));
+        if constexpr (kQuad)
+          asm volatile("" : "+v"(q[t].mr3), "+v"(q[t].mr));
+        else
+          asm volatile("" : "+v"(q[t].mr3), "+v"(q[t].r2));
       }
     }
     // Order 2: a cell (not a leaf: its second moments vanish) adds the

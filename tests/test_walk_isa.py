@@ -6,9 +6,9 @@ machine-sinking switch in build.py, the order in which the next record's load an
 scheduled.  This test compiles the FP32 walk to assembly and checks its hottest loop (the
 monopole forces walk, scalar node loads, two steps per iteration) for the instruction counts the
 step is designed to take: per step 8 vector instructions for the opening test (FP64 offsets, d^2,
-two compares) and 13 for the term (r^2 + eps^2 rounded to FP32, v_rsq_f32, FP32 products,
-conversions and FP64 sums), node records read with scalar loads, no memory traffic through
-vector loads or LDS, no scratch, and eight waves per SIMD.
+two compares) and 12 for the term (r^2 + eps^2 rounded to FP32, v_rsq_f32, three FP32 products,
+one conversion, four FP64 sums, the skip update), node records read with scalar loads, no memory
+traffic through vector loads or LDS, no scratch, and eight waves per SIMD.
 """
 import os
 import re
@@ -79,6 +79,7 @@ def classify(ops):
         "smem": sum(1 for o in ops if o.startswith("s_load")),
         "vmem": sum(1 for o in ops if o.startswith(("global_", "flat_", "buffer_", "scratch_"))),
         "lds": sum(1 for o in ops if o.startswith("ds_")),
+        "cvt64": sum(1 for o in ops if o.startswith("v_cvt_f64_f32")),
     }
 
 
@@ -94,9 +95,11 @@ def test_monopole_walk_loop(asm):
     hot, meta = hot_loops(asm, MONO)
     assert hot, "no scalar-load step loop found in the monopole walk"
     valu = sorted(c["valu"] for c in hot)
-    # 2 steps x (8 test + 13 term) vector instructions; the variants for theta > 1 add the
+    # 2 steps x (8 test + 12 term) vector instructions; the variants for theta > 1 add the
     # particle-range test of the cells that may hold their target
-    assert valu[0] <= 42 and valu[-1] <= 46, f"monopole step loops: {valu} VALU per two steps (designed: 42)"
+    assert valu[0] <= 40 and valu[-1] <= 44, f"monopole step loops: {valu} VALU per two steps (designed: 40)"
+    # one conversion per term (m r^-3 to FP64; the potential takes it too)
+    assert all(c["cvt64"] == 2 for c in hot), "a term converts more than m r^-3 to FP64"
     assert all(c["smem"] <= 4 for c in hot), "a step reads its record in more than two scalar loads"
     assert "; ScratchSize: 0" in meta
     occ = int(re.search(r"; Occupancy: (\d+)", meta).group(1))
@@ -110,7 +113,7 @@ def test_group_theta_walk_loop(asm):
     # the fixed-theta step plus S = fma(l, 1/theta, s)^2 (two FP64 instructions) and a move of s
     # into a vector register (an instruction reads at most one scalar operand, and l and s both
     # come from the scalar record) per step
-    assert valu[0] <= 48 and valu[-1] <= 53, f"per-group-theta step loops: {valu} VALU per two steps (designed: 48)"
+    assert valu[0] <= 46 and valu[-1] <= 50, f"per-group-theta step loops: {valu} VALU per two steps (designed: 46)"
     # (the record's centre, l, mass and next in two loads, s in a third)
     assert min(c["smem"] for c in hot) <= 6, "the step reads its record in more than three scalar loads"
     assert "; ScratchSize: 0" in meta
