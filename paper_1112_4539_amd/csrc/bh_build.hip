@@ -120,13 +120,55 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* __re
   }
 }
 
+// k_scan_apply for at most kScanFuseTiles tiles, without the pass over the
+// tile sums: each block adds up the sums of the tiles before it itself (at most
+// kScanFuseTiles / kScanThreads loads per thread), which saves a launch.
+constexpr int kScanFuseTiles = 2048;
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply_sum(const int32_t* __restrict__ in, int n,
+                                                                  const int32_t* __restrict__ tile_sums,
+                                                                  int32_t* __restrict__ out,
+                                                                  int32_t* __restrict__ total) {
+  __shared__ int tile[kScanTile];
+  __shared__ int lds[kScanThreads / 64];
+  const int t = threadIdx.x;
+  int o = 0;
+  for (int k = t; k < (int)blockIdx.x; k += kScanThreads) o += tile_sums[k];
+  int off;
+  block_excl_scan<kScanThreads>(o, lds, &off);
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r * kScanThreads + t;
+    tile[r * kScanThreads + t] = (i < n) ? in[i] : 0;
+  }
+  __syncthreads();
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k) s += tile[t * kScanItems + k];
+  int tot;
+  int pre = block_excl_scan<kScanThreads>(s, lds, &tot) + off;
+  for (int k = 0; k < kScanItems; ++k) {
+    int v = tile[t * kScanItems + k];
+    tile[t * kScanItems + k] = pre;
+    pre += v;
+  }
+  __syncthreads();
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + r * kScanThreads + t;
+    if (i < n) out[i] = tile[r * kScanThreads + t];
+  }
+  if (total && t == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
+}
+
 hipError_t scan_excl(const int32_t* in, int32_t* out, int n, int32_t* tile_buf, int32_t* total,
                      hipStream_t st) {
   int ntiles = (n + kScanTile - 1) / kScanTile;
   if (ntiles == 0) ntiles = 1;
   k_scan_reduce<<<ntiles, kScanThreads, 0, st>>>(in, n, tile_buf);
-  k_scan_tiles<<<1, 1024, 0, st>>>(tile_buf, ntiles, total);
-  k_scan_apply<<<ntiles, kScanThreads, 0, st>>>(in, n, tile_buf, out);
+  if (ntiles <= kScanFuseTiles) {
+    k_scan_apply_sum<<<ntiles, kScanThreads, 0, st>>>(in, n, tile_buf, out, total);
+  } else {
+    k_scan_tiles<<<1, 1024, 0, st>>>(tile_buf, ntiles, total);
+    k_scan_apply<<<ntiles, kScanThreads, 0, st>>>(in, n, tile_buf, out);
+  }
   return hipGetLastError();
 }
 
