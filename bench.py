@@ -519,11 +519,19 @@ def walk_only(args, bh, inputs):
     T.set_walk_config(args.waves_per_block, args.xcd_chunk, args.target_order, args.lds_share, args.persistent,
                       args.targets_per_lane)
     T.set_order(args.order)
+    tgrp = None
+    if args.theta_group == "uniform":
+        # theta per walk group, every group at --theta (the fixed walk's lists, the per-group step)
+        tgrp = torch.full((T.n_groups,), args.theta, dtype=torch.float32, device=dev)
+    elif args.theta_group == "learned":
+        from paper_1112_4539_amd import learn
+        net, _ = learn.load_net(args.weights)
+        tgrp = learn.scaled_theta(net.infer(T.features(), alpha=1.0, fallback=0.5), args.alpha, 1.0)
     for _ in range(args.walk_only):
-        T.forces(args.theta, spec["eps"])
+        T.forces(args.theta, spec["eps"], theta_group=tgrp)
     torch.cuda.synchronize()
     log(f"[bench] walk-only: {args.workload} n={len(pos)} theta={args.theta} target_order={args.target_order} "
-        f"order={args.order}: {args.walk_only} walks")
+        f"order={args.order} theta_group={args.theta_group}: {args.walk_only} walks")
 
 
 def main():
@@ -551,6 +559,10 @@ def main():
     ap.add_argument("--order", type=int, default=1, help="cell terms: 1 monopole, 2 with the quadrupole")
     ap.add_argument("--quad-theta", type=float, default=0.59,
                     help="also time the quadrupole step at this theta (0: skip)")
+    ap.add_argument("--theta-group", choices=("none", "uniform", "learned"), default="none",
+                    help="walk-only: theta per walk group (every group at --theta, or the shipped network's "
+                         "theta times --alpha)")
+    ap.add_argument("--alpha", type=float, default=0.89, help="walk-only, learned theta: the network's scale")
     ap.add_argument("--walk-only", type=int, default=0, metavar="K",
                     help="only build once and run K force walks of --workload (for profiler runs)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
