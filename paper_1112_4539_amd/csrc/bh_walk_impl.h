@@ -111,7 +111,7 @@ struct AccMixed {
     ax = fma(u.k, u.bx, ax);
     ay = fma(u.k, u.by, ay);
     az = fma(u.k, u.bz, az);
-    p += u.pq - q.mr;
+    p = fma(-q.mr3, q.r2, p + u.pq);
   }
   template <bool kSoft>
   __device__ __forceinline__ void term(double dx, double dy, double dz, double d2, float m, double eps2) {
@@ -467,10 +467,7 @@ __device__ __forceinline__ void walk_step(const WalkArgs& a, Cursor<kF64, kT>& C
 #pragma unroll
       for (int t = 0; t < kT; ++t) {
         q[t] = AccMixed::prep<kSoft>(d2[t], tm, a.eps2);
-        if constexpr (kQuad)
-          asm volatile("" : "+v"(q[t].mr3), "+v"(q[t].mr));
-        else
-          asm volatile("" : "+v"(q[t].mr3), "+v"(q[t].r2));
+        asm volatile("" : "+v"(q[t].mr3), "+v"(q[t].r2));
       }
     }
     // Order 2: a cell (not a leaf: its second moments vanish) adds the
