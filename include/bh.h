@@ -68,7 +68,9 @@ typedef struct bh_walk_config {
 /* Text of the last error of the calling thread ("" if none). */
 BH_API const char *bh_last_error(void);
 
-/* ABI version of this library (bumped on any incompatible change). */
+/* ABI version of this library (bumped on any incompatible change; 3: a
+ * per-group theta, the features and the group errors belong to walk groups,
+ * runs of 64 of the walk's target order, instead of Morton groups). */
 BH_API int bh_version(void);
 
 /* Bytes of workspace a tree of n particles in precision prec needs (an upper

@@ -378,7 +378,7 @@ extern "C" {
 
 const char* bh_last_error(void) { return g_err; }
 
-int bh_version(void) { return 2; }
+int bh_version(void) { return 3; }
 
 int64_t bh_forest_workspace_bytes(int64_t n, int64_t n_clusters, int prec) {
   if (n < 0 || n > kMaxN || n_clusters < 1 || n_clusters > kMaxClusters || (prec != BH_FP32 && prec != BH_FP64))

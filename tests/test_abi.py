@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_side_argument_checks():
     import paper_1112_4539_amd as bh
     lib = bh.load()
-    assert lib.bh_version() == 2
+    assert lib.bh_version() == 3
     assert lib.bh_workspace_bytes(-1, 0) == -1
     assert lib.bh_workspace_bytes(1 << 31, 0) == -1
     assert lib.bh_workspace_bytes(1 << 30, 0) == -1          # indices are 32-bit: n <= 2^30 - 1
