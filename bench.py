@@ -461,6 +461,57 @@ def learned_headline(args, bh, gpos, gmass, eps, n, ref, fixed):
     return out
 
 
+def neighbours_bench(args, bh, inputs):
+    """The general tree walk of Sec. 4.3 as a neighbour search with the SPH density, on the clumpy
+    field N=4,194,304 (FP32, the force headline's field) at radius --radius: each call copies the
+    nodes with their skip radii and walks every particle.  value = neighbour pairs per second."""
+    pos, mass, spec = inputs.make("clumpy4m")
+    n = len(pos)
+    r = args.radius
+    log(f"[bench] neighbours clumpy4m r={r}")
+    dev = torch.device("cuda:0")
+    gpos = torch.tensor(pos.astype(np.float32), device=dev)
+    gmass = torch.tensor(mass.astype(np.float32), device=dev)
+    T = bh.Tree(gpos, gmass)
+    out = T.neighbours(r)
+    cnt = out["count"].to(torch.int64)
+    pairs = int(cnt.sum().item())
+    for _ in range(args.warmup):
+        T.neighbours(r)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        T.neighbours(r)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        p64 = pos.astype(np.float32).astype(np.float64)
+        m64 = mass.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        O = oracle.Tree(p64, m64)
+        t1 = time.perf_counter()
+        w = O.neighbours(r)
+        t2 = time.perf_counter()
+        cpu = {"value": float(np.sum(w["count"])) / (t2 - t0), "unit": "neighbour pairs/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"the whole workload once in FP64: tree build ({t1 - t0:.2f} s) + neighbour walk with "
+                         f"the density of all {n} targets ({t2 - t1:.2f} s)"}
+        log(f"[bench] oracle pairs {int(np.sum(w['count']))} vs kernel {pairs}")
+    line = {"metric": f"neighbour pairs/s with the SPH density, clumpy N={n}, r={r}",
+            "value": pairs / (ms * 1e-3), "unit": "neighbour pairs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, FP32, radius {r}, SPH density (M4, h = r/2)",
+                       "pairs_per_step": pairs, "mean_neighbours": pairs / n, "max_neighbours": int(cnt.max().item()),
+                       "no_neighbour_share": float((cnt == 0).double().mean().item())},
+            "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
 def leapfrog_bench(args, bh, inputs):
     """The time loop on the clumpy field N=4,194,304 (FP32, theta --theta, eps 1e-4): kick-drift-kick
     leapfrog steps with a tree rebuild each step, with the state kept in the caller's (random) order
@@ -559,6 +610,7 @@ def main():
     ap.add_argument("--order", type=int, default=1, help="cell terms: 1 monopole, 2 with the quadrupole")
     ap.add_argument("--quad-theta", type=float, default=0.59,
                     help="also time the quadrupole step at this theta (0: skip)")
+    ap.add_argument("--radius", type=float, default=2e-3, help="neighbours workload: search radius")
     ap.add_argument("--theta-group", choices=("none", "uniform", "learned"), default="none",
                     help="walk-only: theta per walk group (every group at --theta, or the shipped network's "
                          "theta times --alpha)")
@@ -577,6 +629,16 @@ def main():
     from paper_1112_4539_amd import inputs
     from paper_1112_4539_amd import metrics
 
+    if args.copy_calib > 0:
+        # a plain copy of known size: reads and writes exactly MIB MiB each
+        src = torch.ones(args.copy_calib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] copy calibration: 3 x {args.copy_calib} MiB")
+
     if args.workload == "clusters512":
         return forest_bench(args, bh, inputs)
     if args.walk_only:
@@ -587,18 +649,10 @@ def main():
         return learned_bench(args, bh, inputs)
     if args.workload == "cube1m":
         return cube_bench(args, bh, inputs)
+    if args.workload == "neighbours":
+        return neighbours_bench(args, bh, inputs)
     if args.workload == "leapfrog":
         return leapfrog_bench(args, bh, inputs)
-
-    if args.copy_calib > 0:
-        # a plain copy of known size: reads and writes exactly MIB MiB each
-        src = torch.ones(args.copy_calib << 18, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log(f"[bench] copy calibration: 3 x {args.copy_calib} MiB")
 
     pos, mass, spec = inputs.make(args.workload)
     eps = spec["eps"]

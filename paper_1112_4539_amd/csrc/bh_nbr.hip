@@ -13,54 +13,85 @@
 // cell's cube lies within (sqrt(3)/2) l of the cube's centre, itself s from
 // the centre of mass, so a target whose squared distance to the centre of
 // mass is at least R2 has no neighbour in the cell (the factor keeps the
-// bound safe under rounding).  A leaf carries r^2, the exact test.  The
-// neighbour sets therefore equal the definition's, and each target meets its
-// neighbours in depth-first (Morton) order whatever the grouping.
+// bound safe under rounding).  A leaf of one particle carries r^2, the exact
+// test, so cells and leaves take the same test; a leaf of several particles
+// (coincident Morton keys) carries +inf and tests its particles one by one.
+// The neighbour sets therefore equal the definition's, and each target meets
+// its neighbours in depth-first (Morton) order whatever the grouping.
 #include "bh_walk_impl.h"
 
 namespace bh {
 
 namespace {
 
-// W(r, h) of the M4 cubic spline in three dimensions.
-__device__ __forceinline__ double sph_w(double r, double h) {
-  const double q = r / h;
-  const double sig = 1.0 / (3.141592653589793 * h * h * h);
-  if (q < 1.0) return sig * (1.0 - 1.5 * q * q + 0.75 * q * q * q);
-  if (q < 2.0) {
-    const double u = 2.0 - q;
-    return sig * 0.25 * u * u * u;
-  }
-  return 0.0;
+// One node of the neighbour walk, 64 bytes, read with scalar loads.
+//   cx, cy, cz : centre of mass (a one-particle leaf: its particle, exact)
+//   R2         : squared skip radius (cell), r^2 (one-particle leaf), +inf
+//                (leaf of several particles)
+//   m          : mass (a one-particle leaf: its particle's, exact)
+//   next       : first node after the subtree, in (c, cap]
+//   first      : Morton position of the first particle
+//   count      : particles in the subtree
+//   tag        : -1 cell, >= 0 the caller index of a one-particle leaf's
+//                particle, -2 a leaf of several particles
+struct alignas(64) NbrRec {
+  double cx, cy, cz, R2, m;
+  int32_t next, first, count, tag;
+};
+static_assert(sizeof(NbrRec) == 64, "NbrRec must be 64 bytes");
+static_assert(sizeof(NbrRec) == sizeof(WalkNode), "the neighbour walk copy shares the walk copy's storage");
+constexpr int32_t kTagCell = -1, kTagBucket = -2;
+
+template <bool kOff32>
+__device__ __forceinline__ NbrRec nbr_load(const NbrRec* base, int c) {
+  const BH_CONST char* b = kOff32 ? rec_at32(base, c) : (const BH_CONST char*)(uintptr_t)base + (uint64_t)c * 64u;
+  const v8u_t w0 = *(const BH_CONST v8u_t*)b;             // cx, cy, cz, R2
+  const v2u_t w1 = *(const BH_CONST v2u_t*)(b + 32);      // m
+  const v2u_t w2 = *(const BH_CONST v2u_t*)(b + 40);      // next, first
+  const v2u_t w3 = *(const BH_CONST v2u_t*)(b + 48);      // count, tag
+  NbrRec r;
+  r.cx = f64_of(w0.s01);
+  r.cy = f64_of(w0.s23);
+  r.cz = f64_of(w0.s45);
+  r.R2 = f64_of(w0.s67);
+  r.m = f64_of(w1);
+  r.next = (int)w2.x;
+  r.first = (int)w2.y;
+  r.count = (int)w3.x;
+  r.tag = (int)w3.y;
+  return r;
 }
 
 __global__ __launch_bounds__(256) void k_nbr_copy(const Node* __restrict__ nodes, const Counts* __restrict__ cnt,
-                                                  int cap, double radius, WalkNode* __restrict__ out) {
+                                                  const int32_t* __restrict__ perm, int cap, double radius,
+                                                  NbrRec* __restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cap || c >= cnt->n_nodes) return;
   const Node nd = nodes[c];
-  WalkNode w;
+  NbrRec w;
   w.cx = nd.cx;
   w.cy = nd.cy;
   w.cz = nd.cz;
-  if (nd.meta & 1) {
-    w.S = radius * radius;
-  } else {
+  if (!(nd.meta & 1)) {
     const double u = (radius + nd.s + 0.8660254037844387 * nd.l) * (1.0 + 0x1p-40);
-    w.S = u * u;
+    w.R2 = u * u;
+    w.tag = kTagCell;
+  } else if (nd.count == 1) {
+    w.R2 = radius * radius;
+    w.tag = perm[nd.first];
+  } else {
+    w.R2 = __builtin_huge_val();
+    w.tag = kTagBucket;
   }
-  w.M32 = (float)nd.M;
-  w.pad = 0;
+  w.m = nd.M;
   w.next = min(max(nd.next, c + 1), cap);
   w.first = nd.first;
   w.count = nd.count;
-  w.meta = nd.meta;
-  w.M = nd.M;
   out[c] = w;
 }
 
 struct NbrArgs {
-  const WalkNode* wn;          // neighbour walk copy [2n + 1]
+  const NbrRec* wn;            // neighbour walk copy [2n + 1]
   const void* ps;              // float4 / double4 particles in Morton order
   const int32_t* perm;         // Morton position -> caller index
   const int32_t* order;        // walk order of the targets (Morton positions), may be null
@@ -69,7 +100,9 @@ struct NbrArgs {
   const int64_t* seg_off;      // [K + 1] caller offsets of the clusters
   int n_seg;
   int n;
-  double r2, h;
+  double r2;                   // r^2
+  double inv_h;                // 1/h, h = r/2
+  double sig;                  // 1/(pi h^3), the spline's normalisation
   int32_t* count;              // [n] neighbours, caller order
   uint64_t* hash;              // [n] ordered hash of the neighbours' (cluster-relative) caller indices
   int64_t* lists;              // [n][maxlen], may be null
@@ -79,68 +112,147 @@ struct NbrArgs {
 };
 
 struct NbrTarget {
-  double xi, yi, zi, rho;
+  double xi, yi, zi;
+  double wsum;         // m_i + sum over neighbours of m_j w(q_j); the density is sig * wsum
   int i, skip, idx0;
   int32_t count;
   uint64_t h;
-  int64_t len;
   int64_t* list;
 };
 
-template <typename T4>
-__device__ __forceinline__ void nbr_particle(const NbrArgs& a, NbrTarget& T, int k, const T4& q) {
-  const double dx = (double)q.x - T.xi, dy = (double)q.y - T.yi, dz = (double)q.z - T.zi;
+// w(q) = W(|d|, h) / sig of the M4 cubic spline in three dimensions, from
+// d^2 >= 0: 1 - 3/2 q^2 + 3/4 q^3 = 1 + (3/4) q^2 (q - 2) for q < 1,
+// (2 - q)^3 / 4 for 1 <= q < 2, 0 beyond, q = |d|/h.  |d| = sqrt(d^2) by
+// Goldschmidt's iteration from the hardware reciprocal square root (one
+// refinement of the root and of the half reciprocal, then a residual
+// correction: within an ulp or two of the rounded root, far inside the
+// density's tolerance).  2^-1000 is added to d^2, so that the iteration never
+// meets 0 * inf: the sum is d^2 itself for d^2 > 2^-947, and below that q is
+// ~1e-142 or less, where w = 1 to the last bit whatever the root.
+__device__ __forceinline__ double sph_w2(double d2, double inv_h) {
+  const double d2g = d2 + 0x1p-1000;
+  const double y = __builtin_amdgcn_rsq(d2g);
+  double g = d2g * y, hh = 0.5 * y;
+  const double e = fma(-g, hh, 0.5);
+  g = fma(g, e, g);
+  hh = fma(hh, e, hh);
+  g = fma(fma(-g, g, d2g), hh, g);
+  const double q = g * inv_h;
+  const double a = q - 2.0;
+  const double inner = fma(0.75 * (q * q), a, 1.0);
+  const double u = fmax(-a, 0.0);
+  const double outer = (u * u) * (0.25 * u);
+  return q < 1.0 ? inner : outer;
+}
+
+// A wave-uniform coordinate or mass of a bucket particle as an FP64 value in
+// scalar registers, where the other steps hold the record's values.  FP64
+// input is there already.  FP32 input is widened exactly with integer
+// operations on the scalar unit (IEEE 754 binary32 to binary64: the exponent
+// rebiased by 1023 - 127, the fraction shifted by 29; a subnormal normalised
+// from the position of its leading bit; zeros, infinities and NaNs kept), as
+// a vector conversion would leave the value, and every value it meets at a
+// join, in vector registers.
+__device__ __forceinline__ double widen_f32(float x) {
+  const uint32_t f = __builtin_bit_cast(uint32_t, x);
+  const uint64_t sign = (uint64_t)(f >> 31) << 63;
+  const uint32_t e = (f >> 23) & 0xffu, m = f & 0x7fffffu;
+  uint64_t bits;
+  if (e == 0xffu) {
+    bits = sign | (0x7ffull << 52) | ((uint64_t)m << 29);
+  } else if (e != 0) {
+    bits = sign | ((uint64_t)(e + 896u) << 52) | ((uint64_t)m << 29);
+  } else if (m == 0) {
+    bits = sign;
+  } else {
+    // m 2^-149 with its leading bit at position p: 2^(p - 149) (1 + the bits below p)
+    const uint32_t p = 31u - (uint32_t)__builtin_clz(m);
+    bits = sign | ((uint64_t)(p + 874u) << 52) | (((uint64_t)m << (52u - p)) & ((1ull << 52) - 1));
+  }
+  return __builtin_bit_cast(double, bits);
+}
+template <bool kF64, typename F>
+__device__ __forceinline__ double sreg_f64(F x) {
+  if constexpr (kF64) return x; else return widen_f32(x);
+}
+
+template <bool kLists>
+__device__ __forceinline__ void nbr_pair(const NbrArgs& a, NbrTarget& T, int64_t caller, double m, double d2) {
+  const int64_t j = caller - T.idx0;
+  if constexpr (kLists) {
+    if (T.count < a.maxlen) T.list[T.count] = j;
+  }
+  ++T.count;
+  T.h = (T.h ^ ((uint64_t)j << 1)) * kFnvPrime;
+  T.wsum = fma(m, sph_w2(d2, a.inv_h), T.wsum);
+}
+
+// One step at node c: the test (cell: can the target reach it; one-particle
+// leaf: is its particle a neighbour), the successor's record requested as soon
+// as the wave knows it, then the neighbour work of the leaf.  A leaf of several
+// particles takes one step per particle, the cursor staying on it (`sub`, wave
+// uniform, counts its particles), with the particle's position, mass and
+// caller index read beside the record: every neighbour then goes through the
+// same code.
+template <bool kF64, bool kLists, typename Fetch>
+__device__ __forceinline__ void nbr_step(const NbrArgs& a, NbrTarget& T, int& c, int& sub, const NbrRec& rec,
+                                         Fetch fetch) {
+  typedef float v4f_t __attribute__((ext_vector_type(4)));
+  typedef double v4d_t __attribute__((ext_vector_type(4)));
+  using V4 = typename std::conditional<kF64, v4d_t, v4f_t>::type;
+  const int nnext = uniform(rec.next), first = uniform(rec.first), tag = uniform(rec.tag);
+  // (the mass goes with the step's first batch of scalar loads: a load left to
+  // the leaf's branch would cost the step a second round trip)
+  asm volatile("" ::"s"(rec.m));
+  double px = rec.cx, py = rec.cy, pz = rec.cz, pr2 = rec.R2, pm = rec.m;
+  int pk = first, caller = tag, cn_in = c + 1, cn_out = nnext;
+  if (tag == kTagBucket) {
+    const int k = first + sub;
+    const V4 q = *((const BH_CONST V4*)(uintptr_t)a.ps + (uint32_t)k);
+    px = sreg_f64<kF64>(q.x);
+    py = sreg_f64<kF64>(q.y);
+    pz = sreg_f64<kF64>(q.z);
+    pm = sreg_f64<kF64>(q.w);
+    pr2 = a.r2;
+    pk = k;
+    caller = *((const BH_CONST int32_t*)(uintptr_t)a.perm + (uint32_t)k);
+    // (taken here, so that the wait for it stays in this branch: a scalar load
+    // pending at the join would make every step wait for its look-ahead load)
+    asm volatile("" ::"s"(caller));
+    ++sub;
+    if (sub >= uniform(rec.count)) sub = 0;
+    cn_in = cn_out = sub ? c : c + 1;
+  }
+  const bool act = T.skip <= c;
+  const double dx = px - T.xi, dy = py - T.yi, dz = pz - T.zi;
   const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  if (k != T.i && d2 < a.r2) {
-    const int64_t j = (int64_t)a.perm[k] - T.idx0;
-    ++T.count;
-    T.h = (T.h ^ ((uint64_t)j << 1)) * kFnvPrime;
-    if (T.list && T.len < a.maxlen) T.list[T.len] = j;
-    ++T.len;
-    T.rho += (double)q.w * sph_w(sqrt(d2), a.h);
-  }
+  const bool in = d2 < pr2;
+  // (the lanes that enter, as the AND of two compare masks: a ballot of the
+  // combined flag would first turn it into a number)
+  const uint64_t m_in = ballot(act) & __builtin_amdgcn_fcmp(d2, pr2, 4);  // ordered <
+  const int cn = m_in ? cn_in : cn_out;
+  fetch(cn);
+  if (act && !in) T.skip = cn_out;
+  if (caller >= 0 && act && in && pk != T.i) nbr_pair<kLists>(a, T, caller, pm, d2);
+  c = cn;
 }
 
-template <bool kF64, bool kOff32>
+// The subtree [c, end) of one cluster.  The copy has a spare record at
+// cap = 2n and every next pointer is at most cap, so the look-ahead read stays
+// inside it.
+template <bool kF64, bool kLists, bool kOff32>
 __device__ void nbr_subtree(const NbrArgs& a, NbrTarget& T, int c, int end) {
-  using T4 = typename std::conditional<kF64, double4, float4>::type;
-  const T4* __restrict__ ps = reinterpret_cast<const T4*>(a.ps);
-  StepNode<kF64, false> wn;
-  wn.base = a.wn;
+  NbrRec cur = nbr_load<kOff32>(a.wn, c);
+  int sub = 0;
   while (c < end) {
-    const WalkNode cur = wn.template load_at<kOff32>(c);
-    const int nnext = uniform(cur.next);
-    const int first = uniform(cur.first), count = uniform(cur.count), meta = uniform(cur.meta);
-    const bool act = T.skip <= c;
-    if (meta & 1) {
-      // a leaf: proc_particle for its particle(s)
-      if (act) {
-        if (count == 1) {
-          // (a one-particle leaf sits at its particle, and carries its mass exactly)
-          T4 q;
-          q.x = cur.cx;
-          q.y = cur.cy;
-          q.z = cur.cz;
-          q.w = cur.M;
-          nbr_particle(a, T, first, q);
-        } else {
-          for (int k = first; k < first + count; ++k) nbr_particle(a, T, k, ps[k]);
-        }
-      }
-      c = c + 1;
-    } else {
-      // a cell: distance_test; lanes that cannot reach it skip its subtree
-      const double dx = cur.cx - T.xi, dy = cur.cy - T.yi, dz = cur.cz - T.zi;
-      const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      const bool far = !(d2 < cur.S);
-      if (act && far) T.skip = nnext;
-      const uint64_t m_open = ballot(act && !far);
-      c = m_open ? c + 1 : nnext;
-    }
+    NbrRec nx;
+    nbr_step<kF64, kLists>(a, T, c, sub, cur, [&](int cn) { nx = nbr_load<kOff32>(a.wn, cn); });
+    cur = nx;
   }
 }
 
-template <bool kF64>
+// kLists: the caller asked for neighbour lists (a.lists non-null).
+template <bool kF64, bool kLists>
 __global__ __launch_bounds__(64) void k_nbr(NbrArgs a) {
   using T4 = typename std::conditional<kF64, double4, float4>::type;
   using R = typename std::conditional<kF64, double, float>::type;
@@ -159,11 +271,10 @@ __global__ __launch_bounds__(64) void k_nbr(NbrArgs a) {
   T.xi = (double)me.x;
   T.yi = (double)me.y;
   T.zi = (double)me.z;
-  T.rho = valid ? (double)me.w * sph_w(0.0, a.h) : 0.0;
+  T.wsum = (double)me.w;   // the target's own term, w(0) = 1
   T.count = 0;
   T.h = kFnvOffset;
-  T.len = 0;
-  T.list = (a.lists && valid) ? a.lists + (int64_t)a.perm[T.i] * a.maxlen : nullptr;
+  T.list = (kLists && valid) ? a.lists + (int64_t)a.perm[T.i] * a.maxlen : nullptr;
   const int kc = (valid && a.scid) ? min(max(a.scid[T.i], 0), a.n_seg - 1) : 0;
   T.idx0 = valid ? (int)a.seg_off[kc] : 0;
   int klo = valid ? kc : 0x7fffffff, khi = valid ? kc : -1;
@@ -181,15 +292,15 @@ __global__ __launch_bounds__(64) void k_nbr(NbrArgs a) {
     T.skip = (valid && kc == k) ? r0 : 0x7fffffff;
     if (r0 >= r1) continue;
     if (off32)
-      nbr_subtree<kF64, true>(a, T, r0, r1);
+      nbr_subtree<kF64, kLists, true>(a, T, r0, r1);
     else
-      nbr_subtree<kF64, false>(a, T, r0, r1);
+      nbr_subtree<kF64, kLists, false>(a, T, r0, r1);
   }
   if (!valid) return;
   const int o = a.perm[T.i];
   a.count[o] = T.count;
   a.hash[o] = T.h;
-  if (a.rho) reinterpret_cast<R*>(a.rho)[o] = (R)T.rho;
+  if (a.rho) reinterpret_cast<R*>(a.rho)[o] = (R)(a.sig * T.wsum);
 }
 
 }  // namespace
@@ -201,9 +312,10 @@ hipError_t launch_neighbours(bool f64, const Node* nodes, const Counts* counts, 
                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int cap = 2 * n;
-  k_nbr_copy<<<(cap + 255) / 256, 256, 0, st>>>(nodes, counts, cap, radius, copy);
+  NbrRec* rec = reinterpret_cast<NbrRec*>(copy);
+  k_nbr_copy<<<(cap + 255) / 256, 256, 0, st>>>(nodes, counts, perm, cap, radius, rec);
   NbrArgs a{};
-  a.wn = copy;
+  a.wn = rec;
   a.ps = ps;
   a.perm = perm;
   a.order = order;
@@ -213,7 +325,9 @@ hipError_t launch_neighbours(bool f64, const Node* nodes, const Counts* counts, 
   a.n_seg = n_seg;
   a.n = n;
   a.r2 = radius * radius;
-  a.h = 0.5 * radius;
+  const double h = 0.5 * radius;
+  a.inv_h = 1.0 / h;
+  a.sig = 1.0 / (3.141592653589793 * h * h * h);
   a.count = count;
   a.hash = hash;
   a.lists = lists;
@@ -221,10 +335,11 @@ hipError_t launch_neighbours(bool f64, const Node* nodes, const Counts* counts, 
   a.rho = rho;
   a.xcd_chunk = xcd_chunk;
   const int groups = (n + kWave - 1) / kWave;
-  if (f64)
-    k_nbr<true><<<groups, kWave, 0, st>>>(a);
-  else
-    k_nbr<false><<<groups, kWave, 0, st>>>(a);
+  if (f64) {
+    if (lists) k_nbr<true, true><<<groups, kWave, 0, st>>>(a); else k_nbr<true, false><<<groups, kWave, 0, st>>>(a);
+  } else {
+    if (lists) k_nbr<false, true><<<groups, kWave, 0, st>>>(a); else k_nbr<false, false><<<groups, kWave, 0, st>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -69,6 +69,31 @@ def test_neighbours_small(bh, name, radius, prec):
     _compare(bh, pos, mass, prec, radius, maxlen=len(pos))
 
 
+@pytest.mark.parametrize("name,radius", [("duplicates", 0.4), ("coincident", 0.05), ("finest_cell_pair", 0.3)])
+def test_neighbours_subnormal_fp32(bh, name, radius):
+    """Leaves of several particles (coincident Morton keys) read each particle's FP32 position and
+    mass and widen them to FP64: subnormal FP32 coordinates (the case scaled by 1e-39, counts,
+    hashes and lists only, as the density overflows FP32 there) and subnormal FP32 masses (the
+    density checked)."""
+    say(f"[nbr] case={name} fp32 subnormal coordinates, then subnormal masses")
+    pos = tree_cases()[name]
+    rng = np.random.default_rng(len(pos) + 7)
+    mass = rng.random(len(pos)) + 0.5
+    tiny = (pos * 1e-39).astype(np.float32)
+    assert np.any((tiny != 0) & (np.abs(tiny) < np.finfo(np.float32).tiny))
+    T = bh.Tree(*_gpu(tiny, mass, "fp32"))
+    out = T.neighbours(radius * 1e-39, maxlen=len(pos), density=False)
+    torch.cuda.synchronize()
+    w = oracle.Tree(*_seen(tiny, mass, "fp32")).neighbours(radius * 1e-39, maxlen=len(pos))
+    assert w["count"].sum() > 0
+    np.testing.assert_array_equal(out["count"].cpu().numpy(), w["count"])
+    np.testing.assert_array_equal(out["hash"].cpu().numpy().view(np.uint64), w["hash"])
+    np.testing.assert_array_equal(out["lists"].cpu().numpy(), w["lists"])
+    small = (mass * 1e-39).astype(np.float32)
+    assert np.all(small < np.finfo(np.float32).tiny)
+    _compare(bh, pos, small, "fp32", radius, maxlen=len(pos))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_neighbours_clumpy_and_orders(bh, prec):
     say(f"[nbr] clumpy 100k radius 0.005 {prec}, every target order and launch shape")
