@@ -35,21 +35,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(workload, theta):
-    """HBM bytes per walk launch from the committed counter summary, or None.
+def measured_traffic(workload, theta, kind="walk", key="theta"):
+    """HBM bytes per launch of a walk (kind "walk", at theta) or of the neighbour walk (kind "nbr",
+    at the radius: key "radius") from the committed counter summary, or None.
 
     The figure holds only for the kernel source it was counted on: the summary
-    stores a digest of the walk's sources and is ignored once they changed.
+    stores a digest of the kernel's sources and is ignored once they changed.
     """
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"walk_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()
     for p in rec["sources"]:
         h.update(open(os.path.join(ROOT, p), "rb").read())
-    if h.hexdigest() != rec["source_sha256"] or abs(rec.get("theta", theta) - theta) > 1e-12:
+    if h.hexdigest() != rec["source_sha256"] or abs(rec.get(key, theta) - theta) > 1e-12:
         return None
     return rec["traffic_bytes"]
 
@@ -461,6 +462,12 @@ def learned_headline(args, bh, gpos, gmass, eps, n, ref, fixed):
     return out
 
 
+# Algorithmic work of one neighbour pair (i, j within r): the distance test, 8 flops (three
+# differences, three squares, two sums), and the density term, 12 (the square root, q = r/h, the
+# spline's cubic in q, the mass product and the sum).
+FLOPS_PER_NEIGHBOUR_PAIR = 20
+
+
 def neighbours_bench(args, bh, inputs):
     """The general tree walk of Sec. 4.3 as a neighbour search with the SPH density, on the clumpy
     field N=4,194,304 (FP32, the force headline's field) at radius --radius: each call copies the
@@ -486,6 +493,15 @@ def neighbours_bench(args, bh, inputs):
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
+    # the walk kernel alone, bracketed by the tree's HIP events on the stream it runs on
+    T.set_timing(True)
+    kms = []
+    for _ in range(args.steps):
+        T.neighbours(r)
+        kms.append(T.walk_time_ms())
+    T.set_timing(False)
+    kernel_ms = float(np.mean(kms))
+    achieved = FLOPS_PER_NEIGHBOUR_PAIR * pairs / (kernel_ms * 1e-3) / 1e12
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -507,7 +523,15 @@ def neighbours_bench(args, bh, inputs):
             "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
             "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, FP32, radius {r}, SPH density (M4, h = r/2)",
                        "pairs_per_step": pairs, "mean_neighbours": pairs / n, "max_neighbours": int(cnt.max().item()),
-                       "no_neighbour_share": float((cnt == 0).double().mean().item())},
+                       "no_neighbour_share": float((cnt == 0).double().mean().item()),
+                       "walk_kernel_ms": kernel_ms},
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_VALU_TFLOPS,
+                         "traffic": measured_traffic("clumpy4m", r, kind="nbr", key="radius"),
+                         "kernel": "bh::k_nbr<false, false>", "flops_per_unit": FLOPS_PER_NEIGHBOUR_PAIR,
+                         "units_per_launch": pairs,
+                         "peak_note": "FP64 and unpacked FP32 vector rate; the search is bound by its dependent "
+                                      "node-record loads and instruction issue, not by arithmetic"},
             "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 

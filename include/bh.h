@@ -266,8 +266,10 @@ BH_API int bh_tree_export(const bh_tree *t, void *nodes, int32_t *perm, void *st
 BH_API int bh_set_walk_config(bh_tree *t, int waves_per_block, int xcd_chunk, int target_order,
                               int lds_share, int persistent, int targets_per_lane);
 
-/* Enable (1) or disable (0) HIP-event timing of the walk kernel; after a
- * timed walk, bh_walk_time_ms synchronises and returns its duration. */
+/* Enable (1) or disable (0) HIP-event timing of the walk kernel (the force
+ * walk of bh_tree_forces and its variants, or the neighbour walk of
+ * bh_neighbours); after a timed walk, bh_walk_time_ms synchronises and
+ * returns the duration of the last one. */
 BH_API int bh_set_timing(bh_tree *t, int enable);
 BH_API int bh_walk_time_ms(const bh_tree *t, float *ms);
 

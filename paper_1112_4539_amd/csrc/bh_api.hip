@@ -600,8 +600,9 @@ int bh_neighbours(const bh_tree* t, double radius, int32_t* count, uint64_t* has
   hipError_t e = bh::launch_neighbours(t->prec == BH_FP64, t->w.nodes, t->w.counts, t->w.wnodes, t->w.ps, t->w.idx_a,
                                        order, t->n_seg > 1 ? t->w.scid : nullptr, t->w.croot, t->w.seg_off,
                                        (int)t->n_seg, (int)t->n, radius, count, hash, lists, lists ? maxlen : 0, rho,
-                                       chunk, st);
+                                       chunk, t->timing ? t->ev0 : nullptr, t->timing ? t->ev1 : nullptr, st);
   if (e != hipSuccess) return hip_fail(e, "launching the neighbour walk");
+  if (t->timing) const_cast<bh_tree*>(t)->timed = true;
   return BH_OK;
 }
 

@@ -190,7 +190,7 @@ hipError_t launch_neighbours(bool f64, const Node* nodes, const Counts* counts, 
                              const int32_t* perm, const int32_t* order, const int32_t* scid, const int32_t* croot,
                              const int64_t* seg_off, int n_seg, int n, double radius, int32_t* count,
                              uint64_t* hash, int64_t* lists, int64_t maxlen, void* rho, int xcd_chunk,
-                             hipStream_t st);
+                             hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
 
 // Time loop (bh_step.hip): leapfrog updates and the Morton reorder of the state.
 hipError_t launch_kick_drift(bool f64, void* pos, void* vel, const void* acc, int n, double dt, hipStream_t st);
