@@ -107,11 +107,13 @@ def test_neighbours_clumpy_and_orders(bh, prec):
                 assert torch.equal(out[k], ref[k]), (order, chunk, k)
 
 
-def test_neighbours_full_size_sampled(bh):
-    say("[nbr] clumpy4m radius 2e-3 fp32 (sampled targets)")
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_neighbours_full_size_sampled(bh, prec):
+    """The benchmarked search (clumpy 4M, r = 2e-3, the launch bench.py times) on sampled targets."""
+    say(f"[nbr] clumpy4m radius 2e-3 {prec} (sampled targets)")
     pos, mass, spec = inputs.make("clumpy4m")
     tg = inputs.sample_targets(len(pos), 2048, 77)
-    _compare(bh, pos, mass, "fp32", 2e-3, targets=tg)
+    _compare(bh, pos, mass, prec, 2e-3, targets=tg)
 
 
 def test_neighbours_forest(bh):
