@@ -132,8 +132,9 @@ struct NbrTarget {
 };
 
 // w(q) = W(|d|, h) / sig of the M4 cubic spline in three dimensions, from
-// d^2 >= 0: 1 - 3/2 q^2 + 3/4 q^3 = 1 + (3/4) q^2 (q - 2) for q < 1,
-// (2 - q)^3 / 4 for 1 <= q < 2, 0 beyond, q = |d|/h.  |d| = sqrt(d^2) by
+// d^2 >= 0, in its truncated-power form: w = (2 - q)_+^3 / 4 - (1 - q)_+^3
+// (equal to 1 - 3/2 q^2 + 3/4 q^3 for q < 1, (2 - q)^3 / 4 for 1 <= q < 2 and
+// 0 beyond, q = |d|/h), which needs no branch or select.  |d| = sqrt(d^2) by
 // Goldschmidt's iteration from the hardware reciprocal square root (one
 // refinement of the root and of the half reciprocal, then a residual
 // correction: within an ulp or two of the rounded root, far inside the
@@ -149,21 +150,20 @@ __device__ __forceinline__ double sph_w2(double d2, double inv_h) {
   hh = fma(hh, e, hh);
   g = fma(fma(-g, g, d2g), hh, g);
   const double q = g * inv_h;
-  const double a = q - 2.0;
-  const double inner = fma(0.75 * (q * q), a, 1.0);
-  const double u = fmax(-a, 0.0);
-  const double outer = (u * u) * (0.25 * u);
-  return q < 1.0 ? inner : outer;
+  const double u = fmax(2.0 - q, 0.0), b = fmax(1.0 - q, 0.0);
+  return fma(0.25, (u * u) * u, -((b * b) * b));
 }
 
 template <bool kLists>
-__device__ __forceinline__ void nbr_pair(const NbrArgs& a, NbrTarget& T, int64_t caller, double m, double d2) {
-  const int64_t j = caller - T.idx0;
+__device__ __forceinline__ void nbr_pair(const NbrArgs& a, NbrTarget& T, int caller, double m, double d2) {
+  // (j, the caller index relative to the cluster, is in [0, n) with n < 2^30,
+  // so j << 1 is exact in 32 bits and leaves the hash's high word alone)
+  const uint32_t j = (uint32_t)(caller - T.idx0);
   if constexpr (kLists) {
-    if (T.count < a.maxlen) T.list[T.count] = j;
+    if (T.count < a.maxlen) T.list[T.count] = (int64_t)j;
   }
   ++T.count;
-  T.h = (T.h ^ ((uint64_t)j << 1)) * kFnvPrime;
+  T.h = (T.h ^ (uint64_t)(j << 1)) * kFnvPrime;
   T.wsum = fma(m, sph_w2(d2, a.inv_h), T.wsum);
 }
 
