@@ -628,13 +628,24 @@ __device__ __forceinline__ bool same_cell(uint64_t a, uint64_t b, int level) {
 //
 // Keys of different clusters share no cell: such a pair gets split level -1 and
 // bounds every search.
+//
+// The keys of the block's 256 pairs and of kPairHalo keys on either side are
+// staged in LDS first: most cells are small, so most searches stay in the
+// tile, and only those that run past it read the key array in memory.
+constexpr int kPairHalo = 512;
 __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey, const int32_t* __restrict__ ucid,
                                                const Counts* __restrict__ cnt,
                                                int32_t* __restrict__ split, int32_t* __restrict__ rep,
                                                int32_t* __restrict__ pf, int32_t* __restrict__ pl, int nmax) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nmax) return;
+  __shared__ uint64_t tile[256 + 2 * kPairHalo];
   const int U = cnt->n_unique;
+  const int j0 = blockIdx.x * blockDim.x;
+  const int tlo = max(j0 - kPairHalo, 0), thi = min(j0 + (int)blockDim.x + kPairHalo, U);  // keys [tlo, thi)
+  for (int t = threadIdx.x; t < thi - tlo; t += blockDim.x) tile[t] = ukey[tlo + t];
+  __syncthreads();
+  auto key = [&](int m) { return (m >= tlo && m < thi) ? tile[m - tlo] : ukey[m]; };
+  int j = j0 + threadIdx.x;
+  if (j >= nmax) return;
   if (j >= U - 1) {
     rep[j] = 0;
     return;
@@ -645,10 +656,10 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
     rep[j] = 0;
     return;
   }
-  const uint64_t kj = ukey[j], kj1 = ukey[j + 1];
+  const uint64_t kj = key(j), kj1 = key(j + 1);
   const int s = split_level(kj, kj1);
   split[j] = s;
-  auto in_cell = [&](int m, uint64_t ref) { return (!ucid || ucid[m] == cj) && same_cell(ukey[m], ref, s); };
+  auto in_cell = [&](int m, uint64_t ref) { return (!ucid || ucid[m] == cj) && same_cell(key(m), ref, s); };
   // first key of the cell: smallest f <= j with same_cell(ukey[f], kj, s)
   int lo = j, step = 1;
   while (true) {
@@ -681,7 +692,7 @@ __global__ __launch_bounds__(256) void k_pairs(const uint64_t* __restrict__ ukey
     if (in_cell(m, kj1)) c = m; else d = m;
   }
   const int l = c;
-  bool is_rep = (f == j) || (s < kLevels - 1 && same_cell(ukey[f], kj, s + 1));
+  bool is_rep = (f == j) || (s < kLevels - 1 && same_cell(key(f), kj, s + 1));
   rep[j] = is_rep ? 1 : 0;
   pf[j] = f;
   pl[j] = l;
