@@ -73,12 +73,8 @@ __device__ __forceinline__ NbrRec nbr_load(const NbrRec* base, int c) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_nbr_copy(const Node* __restrict__ nodes, const Counts* __restrict__ cnt,
-                                                  const int32_t* __restrict__ perm, int cap, double radius,
-                                                  int group_max, NbrRec* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cap || c >= cnt->n_nodes) return;
-  const Node nd = nodes[c];
+__device__ __forceinline__ NbrRec nbr_record(const Node& nd, int c, const int32_t* __restrict__ perm, int cap,
+                                             double radius, int group_max) {
   NbrRec w;
   w.cx = nd.cx;
   w.cy = nd.cy;
@@ -98,7 +94,45 @@ __global__ __launch_bounds__(256) void k_nbr_copy(const Node* __restrict__ nodes
   w.next = min(max(nd.next, c + 1), cap);
   w.first = nd.first;
   w.count = nd.count;
-  out[c] = w;
+  return w;
+}
+
+// The walk reads the records of the cluster roots, of the cells it descends
+// (cells of more than group_max particles: every node it visits below a root
+// has only such cells above it) and of their children, and never a node
+// inside a group.  So each such cell writes its own record and those of its
+// children that are groups or leaves (a child that is itself such a cell
+// writes its own), and k_nbr_roots writes the roots; the records of nodes
+// inside groups are left as they are.  (Every next pointer the walk follows
+// leads to a sibling of a visited node or of one of its ancestors, a child of
+// a descended cell, or to the end of the cluster's range.)
+__global__ __launch_bounds__(256) void k_nbr_copy(const Node* __restrict__ nodes, const Counts* __restrict__ cnt,
+                                                  const int32_t* __restrict__ perm, int cap, double radius,
+                                                  int group_max, NbrRec* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nn = min(cap, cnt->n_nodes);
+  if (c >= nn) return;
+  const Node nd = nodes[c];
+  if ((nd.meta & 1) || nd.count <= group_max) return;
+  out[c] = nbr_record(nd, c, perm, cap, radius, group_max);
+  const int end = min(max(nd.next, c + 1), nn);
+  int ch = c + 1;
+  for (int k = 0; k < 8 && ch < end; ++k) {
+    const Node cd = nodes[ch];
+    if ((cd.meta & 1) || cd.count <= group_max) out[ch] = nbr_record(cd, ch, perm, cap, radius, group_max);
+    ch = min(max(cd.next, ch + 1), end);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_nbr_roots(const Node* __restrict__ nodes, const Counts* __restrict__ cnt,
+                                                  const int32_t* __restrict__ perm, const int32_t* __restrict__ croot,
+                                                  int n_seg, int cap, double radius, int group_max,
+                                                  NbrRec* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_seg) return;
+  const int c = croot[k];
+  if (c < 0 || c >= min(cap, cnt->n_nodes)) return;
+  out[c] = nbr_record(nodes[c], c, perm, cap, radius, group_max);
 }
 
 struct NbrArgs {
@@ -229,7 +263,9 @@ __device__ __forceinline__ void nbr_step(const NbrArgs& a, NbrTarget& T, int& c,
   // combined flag would first turn it into a number)
   const uint64_t m_in = ballot(act) & __builtin_amdgcn_fcmp(d2, rec.R2, 4);  // ordered <
   const bool cell = tag == kTagCell;
-  const int cn = (m_in && cell) ? c + 1 : nnext;
+  // (next pointers exceed c in every record the walk reads; the max keeps the
+  // cursor moving forward whatever a record holds)
+  const int cn = max((m_in && cell) ? c + 1 : nnext, c + 1);
   fetch(cn);
   if (cell) {
     if (act && !in) T.skip = nnext;
@@ -320,6 +356,7 @@ hipError_t launch_neighbours(bool f64, const Node* nodes, const Counts* counts, 
   const int cap = 2 * n;
   NbrRec* rec = reinterpret_cast<NbrRec*>(copy);
   k_nbr_copy<<<(cap + 255) / 256, 256, 0, st>>>(nodes, counts, perm, cap, radius, kNbrGroup, rec);
+  k_nbr_roots<<<(n_seg + 63) / 64, 64, 0, st>>>(nodes, counts, perm, croot, n_seg, cap, radius, kNbrGroup, rec);
   NbrArgs a{};
   a.wn = rec;
   a.ps = ps;
