@@ -475,10 +475,12 @@ def neighbours_bench(args, bh, inputs):
     pos, mass, spec = inputs.make("clumpy4m")
     n = len(pos)
     r = args.radius
-    log(f"[bench] neighbours clumpy4m r={r}")
+    f64 = args.nbr_prec == "fp64"
+    ft = np.float64 if f64 else np.float32
+    log(f"[bench] neighbours clumpy4m r={r} {args.nbr_prec}")
     dev = torch.device("cuda:0")
-    gpos = torch.tensor(pos.astype(np.float32), device=dev)
-    gmass = torch.tensor(mass.astype(np.float32), device=dev)
+    gpos = torch.tensor(pos.astype(ft), device=dev)
+    gmass = torch.tensor(mass.astype(ft), device=dev)
     T = bh.Tree(gpos, gmass)
     out = T.neighbours(r)
     cnt = out["count"].to(torch.int64)
@@ -505,8 +507,8 @@ def neighbours_bench(args, bh, inputs):
     cpu = None
     if not args.no_cpu:
         import oracle
-        p64 = pos.astype(np.float32).astype(np.float64)
-        m64 = mass.astype(np.float32).astype(np.float64)
+        p64 = pos.astype(ft).astype(np.float64)
+        m64 = mass.astype(ft).astype(np.float64)
         t0 = time.perf_counter()
         O = oracle.Tree(p64, m64)
         t1 = time.perf_counter()
@@ -517,18 +519,20 @@ def neighbours_bench(args, bh, inputs):
                "sample": f"the whole workload once in FP64: tree build ({t1 - t0:.2f} s) + neighbour walk with "
                          f"the density of all {n} targets ({t2 - t1:.2f} s)"}
         log(f"[bench] oracle pairs {int(np.sum(w['count']))} vs kernel {pairs}")
-    line = {"metric": f"neighbour pairs/s with the SPH density, clumpy N={n}, r={r}",
+    line = {"metric": f"neighbour pairs/s with the SPH density, clumpy N={n}, r={r}" + (", FP64" if f64 else ""),
             "value": pairs / (ms * 1e-3), "unit": "neighbour pairs/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-            "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, FP32, radius {r}, SPH density (M4, h = r/2)",
+            "vs_baseline": None, "dtype": "f64" if f64 else "f32+f64", "data": "synthetic",
+            "config": {"workload": f"clumpy field N={n}, seed {spec['seed']}, {'FP64' if f64 else 'FP32'}, radius {r}, "
+                                   "SPH density (M4, h = r/2)",
                        "pairs_per_step": pairs, "mean_neighbours": pairs / n, "max_neighbours": int(cnt.max().item()),
                        "no_neighbour_share": float((cnt == 0).double().mean().item()),
                        "walk_kernel_ms": kernel_ms},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / PEAK_VALU_TFLOPS,
-                         "traffic": measured_traffic("clumpy4m", r, kind="nbr", key="radius"),
-                         "kernel": "bh::k_nbr<false, false>", "flops_per_unit": FLOPS_PER_NEIGHBOUR_PAIR,
+                         "traffic": None if f64 else measured_traffic("clumpy4m", r, kind="nbr", key="radius"),
+                         "kernel": f"bh::k_nbr<{'true' if f64 else 'false'}, false>",
+                         "flops_per_unit": FLOPS_PER_NEIGHBOUR_PAIR,
                          "units_per_launch": pairs,
                          "peak_note": "FP64 and unpacked FP32 vector rate; the search is bound by its dependent "
                                       "node-record loads and instruction issue, not by arithmetic"},
@@ -635,6 +639,7 @@ def main():
     ap.add_argument("--quad-theta", type=float, default=0.59,
                     help="also time the quadrupole step at this theta (0: skip)")
     ap.add_argument("--radius", type=float, default=2e-3, help="neighbours workload: search radius")
+    ap.add_argument("--nbr-prec", choices=("fp32", "fp64"), default="fp32", help="neighbours workload: tree precision")
     ap.add_argument("--theta-group", choices=("none", "uniform", "learned"), default="none",
                     help="walk-only: theta per walk group (every group at --theta, or the shipped network's "
                          "theta times --alpha)")
